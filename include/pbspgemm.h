@@ -1,0 +1,175 @@
+/*
+ * pbspgemm.h -- C ABI of the MI355X (gfx950) PB-SpGEMM library.
+ *
+ * Computes C = A * B for sparse A (m x k, CSC) and B (k x n, CSR) and emits
+ * C in CSR, by the outer-product expand-sort-compress method with
+ * propagation blocking of Gu, Moreira, Edelsohn and Azad (arXiv 2002.11302):
+ *
+ *   symbolic  -- Algorithm 3 (flop = sum_k nnz(A(:,k)) * nnz(B(k,:))), extended
+ *                with the per-row flop count the paper sketches beside it, to
+ *                cut the rows of C into bins of consecutive rows whose
+ *                tuples fit one workgroup's LDS tile (Section 3.2, and the
+ *                variable row ranges of Section 3.4);
+ *   expand    -- Algorithm 2's outer-product loop: every product
+ *                A(r,k) * B(k,c) becomes a tuple appended to the bin of row r
+ *                (Section 3.3);
+ *   sort      -- per-bin radix sort on a packed 32-bit (row-in-bin, column)
+ *                key (Section 3.4, "Preparing integer keys");
+ *   compress  -- per-bin merge of equal keys by addition (Section 3.5);
+ *   ConvertCSR-- row pointers and final positions from a scan over bins in
+ *                row order (Algorithm 2, last step).
+ *
+ * Conventions for every entry point
+ *   - All matrix arrays are DEVICE pointers owned by the caller.  The library
+ *     never allocates device memory: scratch space comes in caller-provided
+ *     workspaces whose sizes the library reports.
+ *   - Index arrays are int32, pointer arrays int64, input values double.
+ *     Inside each column of A / row of B indices strictly increase; ptr[0]
+ *     is 0 and ptr[end] equals nnz.  These array contents are trusted (they
+ *     live on the device); shapes, sizes and null pointers are checked on
+ *     the host before any launch.
+ *   - Stored zeros in A or B are structural, and an output entry whose sum
+ *     cancels to 0.0 stays stored (C keeps every position hit by a product).
+ *   - `hip_stream` is a hipStream_t (NULL = default stream).  Work is
+ *     stream-ordered; an entry point synchronises only where stated.
+ *   - Errors are returned as pb_status; nothing aborts or throws across the
+ *     ABI.  spgemm_last_error() gives a thread-local detail string.
+ */
+#ifndef PBSPGEMM_H
+#define PBSPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PB_OK = 0,
+    PB_ERR_ARG = 1,         /* null pointer, bad enum, bad tuning value */
+    PB_ERR_SHAPE = 2,       /* A.ncols != B.nrows, negative sizes, nnz mismatch with capacity */
+    PB_ERR_RANGE = 3,       /* a dimension >= 2^31, or counts beyond 2^62 */
+    PB_ERR_WORKSPACE = 4,   /* workspace pointer null or smaller than reported */
+    PB_ERR_CAPACITY = 5,    /* C.capacity < nnz(C); *nnzC receives the size needed */
+    PB_ERR_HIP = 6,         /* a HIP runtime call failed (detail in spgemm_last_error) */
+    PB_ERR_UNSUPPORTED = 7, /* a case this build does not handle (detail in spgemm_last_error) */
+    PB_ERR_INTERNAL = 8     /* a device-side consistency check failed */
+} pb_status;
+
+typedef enum {
+    PB_F64 = 0,  /* tuples and C values in double; sums in double */
+    PB_F32C = 1  /* tuples carry fl32(a*b) (product in double, rounded once);
+                    each output is a compensated (Neumaier) float sum; C values float */
+} pb_precision;
+
+/* A compressed sparse matrix.  For CSC, ptr has ncols+1 entries and idx
+ * holds row indices; for CSR, ptr has nrows+1 entries and idx holds column
+ * indices. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    const int64_t *ptr;
+    const int32_t *idx;
+    const double *val;
+} pb_csx;
+
+/* Output C in CSR.  rowptr has nrows(C)+1 entries; colidx / val have room
+ * for `capacity` entries (nnz(C) <= flop, so capacity = flop always fits).
+ * val is double* for PB_F64 and float* for PB_F32C. */
+typedef struct {
+    int64_t *rowptr;
+    int32_t *colidx;
+    void *val;
+    int64_t capacity;
+} pb_csr_out;
+
+/* Tuning knobs; 0 selects the default.
+ *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 1024..8192
+ *   expand_chunk  tuples per expand workgroup: 1024..16384, multiple of 256 */
+typedef struct {
+    int32_t tile_tuples;
+    int32_t expand_chunk;
+    int32_t reserved[6];
+} pb_tune;
+
+/* Plan facts (host copy, filled by the symbolic step). */
+typedef struct {
+    int64_t m, k, n;          /* C is m x n, inner dimension k */
+    int64_t flop;             /* multiplications = number of expanded tuples */
+    int64_t nbins;            /* bins of consecutive rows */
+    int64_t max_bin_tuples;   /* largest bin */
+    int64_t max_row_flop;     /* largest row of C^ */
+    int32_t tile_tuples, expand_chunk;
+    int32_t col_bits;         /* bits of the column part of a packed key */
+    int32_t precision;        /* pb_precision */
+    int64_t count;            /* problems in the plan (1 unless batched) */
+} pb_plan_info;
+
+typedef struct pb_plan pb_plan; /* opaque, host-side */
+
+/*
+ * Symbolic step (Algorithm 3 plus the bin cut).
+ *
+ * Size query: with sym_ws == NULL, writes the symbolic workspace size to
+ * *sym_ws_bytes and returns PB_OK without touching the device.
+ *
+ * Otherwise sym_ws must hold *sym_ws_bytes bytes of device memory; it keeps
+ * the bin tables and must stay alive, unmodified, until the plan's last
+ * numeric call has completed.  The call launches the flop scan, the per-row
+ * flop count and the bin cut on hip_stream, then synchronises the stream
+ * once to read the totals.  On success *plan is a new host-side plan (free it
+ * with spgemm_plan_destroy), *flop the multiplication count and
+ * *workspace_bytes the device workspace spgemm_numeric needs.
+ */
+pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision prec,
+                          const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes,
+                          void *hip_stream, pb_plan **plan, int64_t *flop,
+                          size_t *workspace_bytes);
+
+/*
+ * Numeric step (Algorithm 2: expand into bins, sort and compress each bin,
+ * ConvertCSR).  A_csc / B_csr must be the matrices given to the symbolic
+ * step (same arrays and contents).  workspace holds at least the reported
+ * bytes; its contents need no initialisation and are scratch afterwards.
+ * C->rowptr receives m+1 entries; C->colidx / C->val receive nnz(C)
+ * entries.  If nnzC is non-NULL the stream is synchronised and *nnzC is set
+ * (PB_ERR_CAPACITY if C->capacity was too small: then only the first
+ * `capacity` entries were written and *nnzC is the size needed).  With
+ * nnzC == NULL nothing synchronises; nnz(C) is then C->rowptr[m] on the
+ * device once the stream reaches this point.
+ */
+pb_status spgemm_numeric(pb_plan *plan, const pb_csx *A_csc, const pb_csx *B_csr,
+                         void *workspace, size_t workspace_bytes, pb_csr_out *C,
+                         int64_t *nnzC, void *hip_stream);
+
+/* Copy the plan's facts to *info. */
+pb_status spgemm_plan_info(const pb_plan *plan, pb_plan_info *info);
+
+void spgemm_plan_destroy(pb_plan *plan);
+const char *spgemm_status_string(pb_status s);
+const char *spgemm_last_error(void);
+
+/* ---------------- measurement support ----------------
+ * Kernel timing with HIP events recorded on the launch stream around the
+ * library's own kernels.  Phases: 0 symbolic (all its kernels), 1 expand,
+ * 2 sort+compress (one fused kernel), 3 other numeric kernels.
+ * spgemm_profile_begin clears the accumulators and turns recording on;
+ * spgemm_profile_end waits for the recorded events, turns recording off and
+ * returns, per phase, the summed milliseconds and the number of launches. */
+#define PB_NPHASES 4
+typedef struct {
+    double ms[PB_NPHASES];
+    int64_t launches[PB_NPHASES];
+} pb_profile;
+pb_status spgemm_profile_begin(void);
+pb_status spgemm_profile_end(pb_profile *out);
+
+/* Streaming device copy of `bytes` bytes (16-byte aligned pointers, bytes a
+ * multiple of 16): the bandwidth reference (STREAM Copy analogue of the
+ * paper's Section 4.2) and the calibration kernel for HBM byte counters. */
+pb_status spgemm_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBSPGEMM_H */

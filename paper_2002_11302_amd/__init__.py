@@ -1,0 +1,221 @@
+"""PB-SpGEMM on MI355X: Python binding of libpbspgemm.so.
+
+C = A*B with A in CSC and B in CSR, emitted as CSR, by the outer-product
+expand / bin / sort / compress method of Gu, Moreira, Edelsohn and Azad
+(arXiv 2002.11302, Algorithms 2 and 3).  All arithmetic runs in the HIP
+library; this module only moves pointers, sizes and torch-allocated device
+memory across the C ABI, under the same names as the ABI's entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+from . import _binding as _b
+from ._binding import PHASES, PbError  # noqa: F401
+
+__all__ = [
+    "DeviceCsx", "DeviceCsr", "Plan", "PbError", "PHASES",
+    "spgemm_symbolic", "spgemm_numeric", "spgemm_plan_info", "spgemm_plan_destroy",
+    "spgemm_status_string", "spgemm_last_error", "spgemm_profile_begin", "spgemm_profile_end",
+    "spgemm_copy", "spgemm", "load",
+]
+
+
+def load():
+    """Load the HIP library now (raises if it is not built)."""
+    return _b.lib()
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+@dataclasses.dataclass
+class DeviceCsx:
+    """A CSC or CSR matrix whose arrays are torch tensors on the GPU."""
+
+    nrows: int
+    ncols: int
+    ptr: "object"  # int64 tensor
+    idx: "object"  # int32 tensor
+    val: "object"  # float64 tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.idx.numel())
+
+    @classmethod
+    def from_host(cls, x, device="cuda"):
+        """From any object with nrows, ncols, ptr, idx, val numpy arrays."""
+        torch = _torch()
+        return cls(int(x.nrows), int(x.ncols),
+                   torch.as_tensor(x.ptr, dtype=torch.int64).to(device),
+                   torch.as_tensor(x.idx, dtype=torch.int32).to(device),
+                   torch.as_tensor(x.val, dtype=torch.float64).to(device))
+
+    def transpose_view(self) -> "DeviceCsx":
+        return DeviceCsx(self.ncols, self.nrows, self.ptr, self.idx, self.val)
+
+    def _abi(self) -> _b.PbCsx:
+        for t in (self.ptr, self.idx, self.val):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("DeviceCsx arrays must be contiguous device tensors")
+        assert self.ptr.dtype == _torch().int64 and self.idx.dtype == _torch().int32
+        assert self.val.dtype == _torch().float64
+        return _b.PbCsx(self.nrows, self.ncols, self.nnz, self.ptr.data_ptr(),
+                        self.idx.data_ptr() if self.nnz else None, self.val.data_ptr() if self.nnz else None)
+
+
+@dataclasses.dataclass
+class DeviceCsr:
+    """C in CSR on the GPU (colidx / val trimmed to nnz)."""
+
+    nrows: int
+    ncols: int
+    rowptr: "object"
+    colidx: "object"
+    val: "object"
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colidx.numel())
+
+    def to_host(self) -> dict:
+        return dict(rowptr=self.rowptr.cpu().numpy(), colidx=self.colidx.cpu().numpy(), val=self.val.cpu().numpy())
+
+
+class Plan:
+    """Host-side plan from spgemm_symbolic; keeps its symbolic workspace alive."""
+
+    def __init__(self, handle: int, sym_ws, flop: int, ws_bytes: int, precision: str):
+        self.handle = ctypes.c_void_p(handle)
+        self.sym_ws = sym_ws
+        self.flop = flop
+        self.workspace_bytes = ws_bytes
+        self.precision = precision
+
+    def info(self) -> dict:
+        return spgemm_plan_info(self)
+
+    def close(self):
+        if self.handle:
+            _b.lib().spgemm_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream(stream):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _tune(tune):
+    if tune is None:
+        return None
+    t = _b.PbTune()
+    t.tile_tuples = int(tune.get("tile_tuples", 0))
+    t.expand_chunk = int(tune.get("expand_chunk", 0))
+    return ctypes.byref(t)
+
+
+def spgemm_symbolic(A: DeviceCsx, B: DeviceCsx, precision: str = "f64", tune: dict | None = None,
+                    sym_ws=None, stream=None):
+    """Symbolic step.  With ``sym_ws=None`` returns the symbolic workspace
+    size in bytes (query mode); otherwise returns a :class:`Plan`."""
+    lib = _b.lib()
+    a, b = A._abi(), B._abi()
+    prec = _b.PRECISIONS[precision]
+    nbytes = ctypes.c_size_t(0)
+    if sym_ws is None:
+        _b.check(lib.spgemm_symbolic(ctypes.byref(a), ctypes.byref(b), prec, _tune(tune), None, ctypes.byref(nbytes),
+                                     None, None, None, None), "spgemm_symbolic(query)")
+        return int(nbytes.value)
+    nbytes.value = sym_ws.numel() * sym_ws.element_size()
+    plan = ctypes.c_void_p()
+    flop = ctypes.c_int64()
+    wsb = ctypes.c_size_t()
+    _b.check(lib.spgemm_symbolic(ctypes.byref(a), ctypes.byref(b), prec, _tune(tune), sym_ws.data_ptr(),
+                                 ctypes.byref(nbytes), _stream(stream), ctypes.byref(plan), ctypes.byref(flop),
+                                 ctypes.byref(wsb)), "spgemm_symbolic")
+    return Plan(plan.value, sym_ws, int(flop.value), int(wsb.value), precision)
+
+
+def spgemm_numeric(plan: Plan, A: DeviceCsx, B: DeviceCsx, workspace, C_rowptr, C_colidx, C_val,
+                   sync: bool = True, stream=None):
+    """Numeric step into caller tensors.  Returns nnz(C) when ``sync``."""
+    lib = _b.lib()
+    a, b = A._abi(), B._abi()
+    cap = int(C_colidx.numel())
+    out = _b.PbCsrOut(C_rowptr.data_ptr(), C_colidx.data_ptr() if cap else None,
+                      C_val.data_ptr() if cap else None, cap)
+    nnz = ctypes.c_int64(-1)
+    wsp = workspace.data_ptr() if workspace is not None and workspace.numel() else None
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _b.check(lib.spgemm_numeric(plan.handle, ctypes.byref(a), ctypes.byref(b), wsp, wsb, ctypes.byref(out),
+                                ctypes.byref(nnz) if sync else None, _stream(stream)), "spgemm_numeric")
+    return int(nnz.value) if sync else None
+
+
+def spgemm_plan_info(plan: Plan) -> dict:
+    info = _b.PbPlanInfo()
+    _b.check(_b.lib().spgemm_plan_info(plan.handle, ctypes.byref(info)), "spgemm_plan_info")
+    return {name: getattr(info, name) for name, _ in _b.PbPlanInfo._fields_}
+
+
+def spgemm_plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+def spgemm_status_string(status: int) -> str:
+    return _b.status_string(status)
+
+
+def spgemm_last_error() -> str:
+    return _b.last_error()
+
+
+def spgemm_profile_begin() -> None:
+    _b.check(_b.lib().spgemm_profile_begin(), "spgemm_profile_begin")
+
+
+def spgemm_profile_end() -> dict:
+    prof = _b.PbProfile()
+    _b.check(_b.lib().spgemm_profile_end(ctypes.byref(prof)), "spgemm_profile_end")
+    return {name: (prof.ms[i], prof.launches[i]) for i, name in enumerate(PHASES)}
+
+
+def spgemm_copy(dst, src, nbytes: int, stream=None) -> None:
+    _b.check(_b.lib().spgemm_copy(dst.data_ptr(), src.data_ptr(), int(nbytes), _stream(stream)), "spgemm_copy")
+
+
+def _alloc_bytes(n: int, device):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+def spgemm(A: DeviceCsx, B: DeviceCsx, precision: str = "f64", tune: dict | None = None, stream=None) -> DeviceCsr:
+    """C = A*B (A CSC, B CSR) on the GPU; allocation through torch."""
+    torch = _torch()
+    dev = A.ptr.device
+    nsym = spgemm_symbolic(A, B, precision, tune)
+    sym_ws = _alloc_bytes(nsym, dev)
+    plan = spgemm_symbolic(A, B, precision, tune, sym_ws=sym_ws, stream=stream)
+    try:
+        ws = _alloc_bytes(plan.workspace_bytes, dev)
+        rowptr = torch.empty(A.nrows + 1, dtype=torch.int64, device=dev)
+        cap = max(plan.flop, 1)
+        colidx = torch.empty(cap, dtype=torch.int32, device=dev)
+        val = torch.empty(cap, dtype=torch.float64 if precision == "f64" else torch.float32, device=dev)
+        nnz = spgemm_numeric(plan, A, B, ws, rowptr, colidx, val, sync=True, stream=stream)
+    finally:
+        plan.close()
+    return DeviceCsr(A.nrows, B.ncols, rowptr, colidx[:nnz], val[:nnz])

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Structure (row pointers and column indices) must match bit for bit.  Values
+are compared against N = |A||B| of each entry (for non-negative inputs N is
+the value itself, so this is the relative error): FP64 within 1e-12, FP32
+tuples with compensated merge within 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Csx, csc_to_csr, er_problem, identity, random_sparse
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32c": 1e-6}
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_11302_amd as pbm
+
+    pbm.load()
+    return pbm
+
+
+def _run(pb, a: Csx, b: Csx, precision="f64", tune=None):
+    A = pb.DeviceCsx.from_host(a)
+    B = pb.DeviceCsx.from_host(b)
+    c = pb.spgemm(A, B, precision=precision, tune=tune)
+    return c.to_host()
+
+
+def _compare(got: dict, ref: dict, precision: str, exact_values=False):
+    assert np.array_equal(got["rowptr"], ref["rowptr"]), "row pointers differ"
+    assert np.array_equal(got["colidx"], ref["colidx"]), "column indices differ"
+    gv = got["val"].astype(np.float64)
+    if exact_values:
+        assert np.array_equal(gv, ref["val"])
+        return 0.0
+    err = np.abs(gv - ref["val"])
+    bound = TOL[precision] * ref["absval"]
+    bad = err > bound
+    worst = float(np.max(np.where(ref["absval"] > 0, err / np.where(ref["absval"] > 0, ref["absval"], 1), err))) if err.size else 0.0
+    assert not np.any(bad), f"{int(bad.sum())} values beyond {TOL[precision]} x N; worst ratio {worst:.3e}"
+    return worst
+
+
+def _check_invariants(got: dict, flop: int):
+    rp, ci = got["rowptr"], got["colidx"]
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == len(ci)
+    assert len(ci) <= flop
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    key = rows.astype(np.int64) * (int(ci.max()) + 1 if len(ci) else 1) + ci
+    assert np.all(np.diff(key) > 0), "columns must strictly increase within rows"
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_er_4096_d4_square(pb, precision):
+    _say(f"ER n=4096 d=4 A*A {precision}")
+    a, b = er_problem(4096, 4, 1, None)
+    ref = oracle.spgemm(a, b)
+    got = _run(pb, a, b, precision)
+    _compare(got, ref, precision)
+    _check_invariants(got, ref["flop"])
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_er_signed_several_tiles(pb, precision):
+    _say(f"ER n=60000 d=8 signed {precision}")
+    a, b = er_problem(60000, 8, 5, 6, values="signed")
+    ref = oracle.spgemm(a, b)
+    got = _run(pb, a, b, precision)
+    _compare(got, ref, precision)
+
+
+@pytest.mark.parametrize("tile", [256, 1000, 4096])
+@pytest.mark.parametrize("chunk", [2048, 4096])
+def test_tiles_and_chunks(pb, tile, chunk):
+    _say(f"ER n=20011 d=6 tile={tile} chunk={chunk}")
+    a, b = er_problem(20011, 6, 7, 8)
+    ref = oracle.spgemm(a, b)
+    got = _run(pb, a, b, "f64", tune={"tile_tuples": tile, "expand_chunk": chunk})
+    _compare(got, ref, "f64")
+
+
+def test_rectangular_with_dense_and_empty_lines(pb):
+    _say("rectangular 3000x700x2500 with dense/empty rows and columns")
+    a = random_sparse(3000, 700, 0.002, 11, "csc", values="signed", dense_rows=(17,), empty_cols=(0, 5, 699))
+    b = random_sparse(700, 2500, 0.001, 12, "csr", values="signed", dense_cols=(3,), empty_rows=(2, 600))
+    ref = oracle.spgemm(a, b)
+    got = _run(pb, a, b, "f64")
+    _compare(got, ref, "f64")
+
+
+def test_isolated_big_rows_small_tile(pb):
+    # rows whose flop exceeds tile/2 become single-row bins
+    _say("isolated big rows with tile=512")
+    a = random_sparse(900, 400, 0.01, 21, "csc", dense_rows=(5, 6, 400, 899))
+    b = random_sparse(400, 700, 0.0015, 22, "csr")
+    ref = oracle.spgemm(a, b)
+    got = _run(pb, a, b, "f64", tune={"tile_tuples": 512})
+    _compare(got, ref, "f64")
+
+
+def test_integer_values_bit_exact(pb):
+    _say("integer-valued inputs, exact sums")
+    a = random_sparse(2000, 1500, 0.004, 31, "csc", values="int")
+    b = random_sparse(1500, 1800, 0.004, 32, "csr", values="int")
+    ref = oracle.spgemm(a, b)
+    got = _run(pb, a, b, "f64")
+    _compare(got, ref, "f64", exact_values=True)
+    got32 = _run(pb, a, b, "f32c")
+    _compare(got32, ref, "f32c", exact_values=True)  # small integers are exact in float too
+
+
+def test_identity_products(pb):
+    _say("A*I and I*B")
+    a = random_sparse(5000, 3000, 0.002, 41, "csc", values="signed")
+    got = _run(pb, a, identity(3000, "csr"), "f64")
+    ar = csc_to_csr(a)
+    assert np.array_equal(got["rowptr"], ar.ptr) and np.array_equal(got["colidx"], ar.idx)
+    assert np.array_equal(got["val"], ar.val)
+    b = random_sparse(3000, 4000, 0.002, 42, "csr", values="signed")
+    got = _run(pb, identity(3000, "csc"), b, "f64")
+    assert np.array_equal(got["rowptr"], b.ptr) and np.array_equal(got["colidx"], b.idx)
+    assert np.array_equal(got["val"], b.val)
+
+
+def test_empty_and_degenerate(pb):
+    _say("empty / degenerate shapes")
+    for (m, k, n, dens) in [(100, 50, 80, 0.0), (1, 1, 1, 1.0), (64, 1, 64, 0.5), (300, 200, 1, 0.05), (0, 10, 10, 0.1), (10, 0, 10, 0.1)]:
+        a = random_sparse(m, k, dens, 51, "csc") if m and k else Csx(m, k, np.zeros(k + 1, np.int64), np.zeros(0, np.int32), np.zeros(0), "csc")
+        b = random_sparse(k, n, dens, 52, "csr") if k and n else Csx(k, n, np.zeros(k + 1, np.int64), np.zeros(0, np.int32), np.zeros(0), "csr")
+        ref = oracle.spgemm(a, b) if m else dict(rowptr=np.zeros(1, np.int64), colidx=np.zeros(0, np.int32), val=np.zeros(0), absval=np.zeros(0))
+        got = _run(pb, a, b, "f64")
+        _compare(got, ref, "f64")
+
+
+def test_cancellation_stays_stored(pb):
+    _say("exact cancellation")
+    # A = [[1, 1]], B = [[1], [-1]]
+    a = Csx(1, 2, np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), np.array([1.0, 1.0]), "csc")
+    b = Csx(2, 1, np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), np.array([1.0, -1.0]), "csr")
+    got = _run(pb, a, b, "f64")
+    assert list(got["rowptr"]) == [0, 1] and list(got["colidx"]) == [0] and got["val"][0] == 0.0
+
+
+def test_tile_invariance(pb):
+    _say("structure independent of tile / chunk")
+    a, b = er_problem(30000, 7, 61, 62, values="signed")
+    base = _run(pb, a, b, "f64")
+    for tune in ({"tile_tuples": 300}, {"tile_tuples": 2048, "expand_chunk": 2048}):
+        got = _run(pb, a, b, "f64", tune=tune)
+        assert np.array_equal(got["rowptr"], base["rowptr"]) and np.array_equal(got["colidx"], base["colidx"])
+        assert np.allclose(got["val"], base["val"], rtol=0, atol=1e-12)
+
+
+def test_oversize_rows_rejected(pb):
+    _say("row with more tuples than the tile")
+    a = random_sparse(200, 300, 0.01, 71, "csc", dense_rows=(3,))
+    b = random_sparse(300, 400, 0.05, 72, "csr")
+    with pytest.raises(pb.PbError) as ei:
+        _run(pb, a, b, "f64", tune={"tile_tuples": 256})
+    assert ei.value.name == "PB_ERR_UNSUPPORTED"
+
+
+def test_capacity_error_reports_size(pb):
+    import torch
+
+    _say("capacity too small")
+    a, b = er_problem(3000, 4, 81, 82)
+    A = pb.DeviceCsx.from_host(a)
+    B = pb.DeviceCsx.from_host(b)
+    nsym = pb.spgemm_symbolic(A, B)
+    plan = pb.spgemm_symbolic(A, B, sym_ws=torch.empty(nsym, dtype=torch.uint8, device="cuda"))
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+    rowptr = torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda")
+    colidx = torch.empty(100, dtype=torch.int32, device="cuda")
+    val = torch.empty(100, dtype=torch.float64, device="cuda")
+    with pytest.raises(pb.PbError) as ei:
+        pb.spgemm_numeric(plan, A, B, ws, rowptr, colidx, val)
+    assert ei.value.name == "PB_ERR_CAPACITY"
+    ref = oracle.spgemm(a, b)
+    assert int(rowptr[-1].item()) == len(ref["colidx"])
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_er_2e20_d16_full_size_sampled(pb, precision):
+    """The benchmark workload at full size: sampled rows against the
+    oracle, invariants on all of C."""
+    import torch
+
+    _say(f"ER n=2^20 d=16 A*B full size {precision}")
+    a, b = er_problem(1 << 20, 16, 2, 3)
+    A = pb.DeviceCsx.from_host(a)
+    B = pb.DeviceCsx.from_host(b)
+    c = pb.spgemm(A, B, precision=precision)
+    flop = 16 * 16 * (1 << 20)
+    rp = c.rowptr.cpu().numpy()
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == c.nnz <= flop
+    # strictly increasing columns inside each row (checked on the device)
+    ci = c.colidx
+    rows = torch.repeat_interleave(torch.arange(a.nrows, device="cuda"), torch.diff(c.rowptr))
+    same_row = rows[1:] == rows[:-1]
+    assert bool(torch.all((ci[1:] > ci[:-1]) | ~same_row).item())
+    rng = np.random.default_rng(99)
+    sample = np.unique(np.concatenate([[0, 1, a.nrows - 1], rng.integers(0, a.nrows, 3000)]))
+    ref = oracle.spgemm_rows(a, b, sample)
+    cv = c.val.cpu().numpy().astype(np.float64)
+    cc = ci.cpu().numpy()
+    for s, r in enumerate(sample):
+        lo, hi = rp[r], rp[r + 1]
+        rlo, rhi = ref["ptr"][s], ref["ptr"][s + 1]
+        assert np.array_equal(cc[lo:hi], ref["idx"][rlo:rhi]), f"row {r} structure"
+        err = np.abs(cv[lo:hi] - ref["val"][rlo:rhi])
+        assert np.all(err <= TOL[precision] * ref["absval"][rlo:rhi]), f"row {r} values"
