@@ -152,7 +152,8 @@ const char *spgemm_last_error(void);
 /* ---------------- measurement support ----------------
  * Kernel timing with HIP events recorded on the launch stream around the
  * library's own kernels.  Phases: 0 symbolic (all its kernels), 1 expand,
- * 2 sort+compress (one fused kernel), 3 other numeric kernels.
+ * 2 sort+compress (one fused kernel), 3 entries per row of C and the
+ * row-pointer scan.
  * spgemm_profile_begin clears the accumulators and turns recording on;
  * spgemm_profile_end waits for the recorded events, turns recording off and
  * returns, per phase, the summed milliseconds and the number of launches. */

@@ -19,7 +19,7 @@ STATUS_NAMES = {
 }
 PRECISIONS = {"f64": 0, "f32c": 1}
 PB_NPHASES = 4
-PHASES = ("symbolic", "expand", "sort_compress", "numeric_other")
+PHASES = ("symbolic", "expand", "sort_compress", "row_counts")
 
 
 class PbError(RuntimeError):

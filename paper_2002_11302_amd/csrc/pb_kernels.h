@@ -63,11 +63,14 @@ __global__ __launch_bounds__(BLOCK) void k_chained_scan(int64_t n, Src src, Dst 
     if (lane_id() == 0) s_side[threadIdx.x / kWave] = side;
     uint64_t tile_total;
     const uint64_t texcl = block_excl_scan<BLOCK, Op>(local, s_tmp, tile_total);
-    if (threadIdx.x == 0) {
-        uint64_t mx = 0;
-        for (int i = 0; i < NW; ++i) mx = s_side[i] > mx ? s_side[i] : mx;
-        dst.side_commit(mx);
-        s_tmp[NW + 1] = look_back<Op>(status, tile, tile_total, err);
+    if (threadIdx.x < kWave) {
+        if (threadIdx.x == 0) {
+            uint64_t mx = 0;
+            for (int i = 0; i < NW; ++i) mx = s_side[i] > mx ? s_side[i] : mx;
+            dst.side_commit(mx);
+        }
+        const uint64_t ex = look_back_wave<Op>(status, tile, tile_total, err);
+        if (threadIdx.x == 0) s_tmp[NW + 1] = ex;
     }
     __syncthreads();
     uint64_t run = Op::combine(s_tmp[NW + 1], texcl);
@@ -104,11 +107,14 @@ struct ColFlopDst : NoSide {
 };
 
 // Per-row flop: rowflop[r] = sum over k with A(r,k) stored of nnz(B(k,:)).
-// One thread per column of A; columns longer than 32 entries are taken by
-// the whole wave, lanes striding over the column.
+// The counter update for A entry e returns the flop already counted in its
+// row, which becomes the offset of e's run inside the row's tuple range
+// (runpos[e]); the expand then writes every run to a fixed place without
+// atomics.  One thread per column of A; columns longer than 32 entries are
+// taken by the whole wave, lanes striding over the column.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp, const int32_t *ari,
-                                                   const int64_t *brp, uint64_t *rowflop) {
+                                                   const int64_t *brp, uint64_t *rowflop, uint32_t *runpos) {
     const int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     int64_t a0 = 0, na = 0, nb = 0;
     if (k < K) {
@@ -119,7 +125,8 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
     }
     const bool longcol = na > 32;
     if (!longcol) {
-        for (int64_t e = a0; e < a0 + na; ++e) atomic_add_agent(&rowflop[ari[e]], (uint64_t)nb);
+        for (int64_t e = a0; e < a0 + na; ++e)
+            runpos[e] = (uint32_t)atomic_add_agent(&rowflop[ari[e]], (uint64_t)nb);
     }
     uint64_t mask = ballot(longcol);
     const uint32_t lane = lane_id();
@@ -129,7 +136,8 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
         const int64_t la0 = __shfl(a0, L, kWave);
         const int64_t lna = __shfl(na, L, kWave);
         const int64_t lnb = __shfl(nb, L, kWave);
-        for (int64_t e = la0 + lane; e < la0 + lna; e += kWave) atomic_add_agent(&rowflop[ari[e]], (uint64_t)lnb);
+        for (int64_t e = la0 + lane; e < la0 + lna; e += kWave)
+            runpos[e] = (uint32_t)atomic_add_agent(&rowflop[ari[e]], (uint64_t)lnb);
     }
 }
 
@@ -194,8 +202,16 @@ struct BinSrc {
         return start ? ((1ull << 31) | (uint64_t)r) : 0;
     }
 };
+// Per-row facts the expand needs: where the row's tuples start in the
+// row-ordered tuple array, and the row's index inside its bin.
+struct RowTab {
+    int64_t base;
+    uint32_t rl;
+    uint32_t bin;
+};
+
 struct BinDst {
-    uint64_t *rowinfo;
+    RowTab *rowtab;
     int32_t *binrow0;
     int64_t *binoff;
     const uint64_t *R;
@@ -206,7 +222,11 @@ struct BinDst {
         const uint64_t incl = BinOp::combine(excl, e);
         const uint64_t bin = (incl >> 31) - 1;
         const uint64_t l = incl & 0x7fffffffull;
-        rowinfo[r] = (bin << 32) | (uint64_t)(r - (int64_t)l);
+        RowTab rt;
+        rt.base = (int64_t)R[r];
+        rt.rl = (uint32_t)(r - (int64_t)l);
+        rt.bin = (uint32_t)bin;
+        rowtab[r] = rt;
         if (e) {
             binrow0[bin] = (int32_t)r;
             binoff[bin] = (int64_t)R[r];
@@ -239,11 +259,11 @@ __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64
 // cut into chunks of C = BLOCK*IPT tuples; tuple t lies in column k of A /
 // row k of B with F[k] <= t < F[k+1], and is the product of the i-th entry
 // of A(:,k) and the j-th entry of B(k,:), (i, j) = divmod(t - F[k], nnz(B(k,:))).
-// The tuples from one A entry form a run bound for one bin (its row's);
-// the run's first tuple in the chunk reserves room for the whole run piece
-// with one atomic on the bin cursor, so each run lands contiguously and
-// consecutive lanes write consecutive addresses (the GPU counterpart of the
-// paper's cache-line-sized local bins, Section 3.3).
+// The tuples of one A entry e = (r, k) form a run that goes to row r's
+// range of the row-ordered tuple array, at offset runpos[e] (fixed by the
+// symbolic step), so bins are contiguous row ranges and no append needs an
+// atomic.  Consecutive lanes take consecutive tuples, so each run is written
+// by consecutive lanes to consecutive addresses.
 struct ExpandArgs {
     int64_t flop, K;
     const int64_t *F;
@@ -254,20 +274,44 @@ struct ExpandArgs {
     const int64_t *brp;
     const int32_t *bci;
     const double *bv;
-    const uint64_t *rowinfo;
-    const int64_t *binoff;
-    uint32_t *bincur;
+    const uint32_t *runpos;
+    const RowTab *rowtab;
     uint32_t *keys;
     void *vals;
     int cb;
     uint32_t *err;
 };
 
+// (q, r) = divmod(x, d) for 0 <= x, 1 <= d; float reciprocal with an exact
+// integer correction when x < 2^24, integer division otherwise.
+__device__ __forceinline__ void divmod_u(int64_t x, int64_t d, int64_t &q, int64_t &r) {
+    if (x < (1 << 24) && d < (1 << 24)) {
+        int32_t qq = (int32_t)((float)x * __builtin_amdgcn_rcpf((float)d));
+        int32_t rr = (int32_t)x - qq * (int32_t)d;
+        while (rr < 0) {
+            --qq;
+            rr += (int32_t)d;
+        }
+        while (rr >= (int32_t)d) {
+            ++qq;
+            rr -= (int32_t)d;
+        }
+        q = qq;
+        r = rr;
+    } else if (x < 0x100000000ll && d < 0x100000000ll) {
+        const uint32_t qq = (uint32_t)x / (uint32_t)d;
+        q = qq;
+        r = x - (int64_t)qq * d;
+    } else {
+        q = x / d;
+        r = x - q * d;
+    }
+}
+
 template <int BLOCK, int IPT, int WMAX, class VT>
 __global__ __launch_bounds__(BLOCK) void k_expand(ExpandArgs a) {
     constexpr int C = BLOCK * IPT;
     __shared__ int64_t s_F[WMAX];
-    __shared__ uint32_t s_base[C];
     const int64_t c = blockIdx.x;
     const int64_t t0 = c * (int64_t)C;
     const int64_t t1 = (t0 + C < a.flop) ? t0 + C : a.flop;
@@ -279,92 +323,175 @@ __global__ __launch_bounds__(BLOCK) void k_expand(ExpandArgs a) {
         for (int64_t i = threadIdx.x; i < nwin; i += BLOCK) s_F[i] = a.F[k0 + i];
     __syncthreads();
 
-    uint32_t r_bin[IPT], r_lpos[IPT], r_key[IPT];
-    VT r_val[IPT];
     VT *vals = (VT *)a.vals;
-#pragma unroll
+    int64_t kw = 0;  // current column relative to k0 (windowed path)
+#pragma unroll 4
     for (int it = 0; it < IPT; ++it) {
         const int64_t t = t0 + it * BLOCK + threadIdx.x;
-        if (t < t1) {
-            int64_t k, Fk;
-            if (windowed) {
-                const int64_t j = last_le(s_F, 0, nwin - 1, t);
-                k = k0 + j;
-                Fk = s_F[j];
-            } else {
-                k = last_le(a.F, k0, kl + 1, t);
-                Fk = a.F[k];
+        if (t >= t1) break;
+        int64_t k, Fk;
+        if (windowed) {
+            // items of a thread ascend: advance from the previous column
+            int steps = 0;
+            while (s_F[kw + 1] <= t && steps < 8) {
+                ++kw;
+                ++steps;
             }
-            const int64_t off = t - Fk;
-            const int64_t bs = a.brp[k];
-            const int64_t nb = a.brp[k + 1] - bs;
-            int64_t i, j;
-            if (off < 0x100000000ll && nb < 0x100000000ll) {
-                const uint32_t q = (uint32_t)off / (uint32_t)nb;
-                i = q;
-                j = off - (int64_t)q * nb;
-            } else {
-                i = off / nb;
-                j = off - i * nb;
-            }
-            const int64_t e = a.acp[k] + i;
-            const int32_t r = a.ari[e];
-            const uint64_t info = a.rowinfo[r];
-            const uint32_t bin = (uint32_t)(info >> 32);
-            const uint32_t rl = (uint32_t)info;
-            const int64_t q = bs + j;
-            const uint32_t col = (uint32_t)a.bci[q];
-            const double prod = a.av[e] * a.bv[q];
-            const int64_t lstart = (t - j > t0) ? t - j : t0;
-            if (j == 0 || t == t0) {
-                const int64_t rest = nb - j;
-                const int64_t len = (rest < t1 - t) ? rest : t1 - t;
-                s_base[t - t0] = atomic_add_agent(&a.bincur[bin], (uint32_t)len);
-            }
-            r_bin[it] = bin;
-            r_lpos[it] = (uint32_t)(lstart - t0);
-            r_key[it] = (rl << a.cb) | col;
-            r_val[it] = (VT)prod;
+            if (s_F[kw + 1] <= t) kw = last_le(s_F, kw, nwin - 1, t);
+            k = k0 + kw;
+            Fk = s_F[kw];
+        } else {
+            k = last_le(a.F, k0, kl + 1, t);
+            Fk = a.F[k];
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-        const int64_t t = t0 + it * BLOCK + threadIdx.x;
-        if (t < t1) {
-            const uint32_t bin = r_bin[it];
-            const int64_t slot = a.binoff[bin] + (int64_t)s_base[r_lpos[it]] + (t - t0 - r_lpos[it]);
-            if (slot < a.binoff[bin + 1]) {
-                a.keys[slot] = r_key[it];
-                vals[slot] = r_val[it];
-            } else {
-                atomic_or_agent(a.err, (uint32_t)kErrBinOverflow);
-            }
+        const int64_t bs = a.brp[k];
+        const int64_t nb = a.brp[k + 1] - bs;
+        int64_t i, j;
+        divmod_u(t - Fk, nb, i, j);
+        const int64_t e = a.acp[k] + i;
+        const int32_t r = a.ari[e];
+        const RowTab rt = a.rowtab[r];
+        const int64_t slot = rt.base + (int64_t)a.runpos[e] + j;
+        const int64_t q = bs + j;
+        const uint32_t key = (rt.rl << a.cb) | (uint32_t)a.bci[q];
+        const double prod = a.av[e] * a.bv[q];
+        if (slot < a.flop) {
+            a.keys[slot] = key;
+            vals[slot] = (VT)prod;
+        } else {
+            atomic_or_agent(a.err, (uint32_t)kErrBinOverflow);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Sort + compress + ConvertCSR, one workgroup per bin, bins claimed in row
-// order by ticket.  The bin's N <= TMAX tuples are loaded once; keys are
-// radix-sorted in LDS (stable LSD, <= 8-bit digits, per-wave ballot ranking)
-// together with 16-bit slot numbers; the values stay in registers until the
-// keys are sorted and are then parked in LDS by slot.  Equal keys are summed
-// in sorted order by the first tuple of each run (Section 3.5's merge), the
-// bin's entry count goes through a decoupled look-back over bins to give
-// its offset in C, and row pointers of the bin's rows are written from the
-// sorted keys (Algorithm 2's ConvertCSR).
+// ConvertCSR, part 1: entries per row of C.  The tuple array is in row
+// order (each row's tuples are contiguous), so nnz(C(r,:)) is the number of
+// distinct keys among row r's tuples.  One workgroup per bin inserts the
+// bin's keys into an LDS hash set (open addressing, linear probing); the
+// first insertion of a key counts for its row.  Only keys are read.
+struct CountArgs {
+    const int32_t *binrow0;
+    const int64_t *binoff;
+    const uint32_t *keys;
+    int cb;
+    uint32_t *rownnz;
+    uint32_t *err;
+};
+
+template <int BLOCK, int TMAX>
+__global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
+    constexpr int TS = 2 * TMAX;  // table slots, load factor <= 1/2
+    constexpr int LOG_TS = (TS >= 16384) ? 14 : (TS >= 8192) ? 13 : (TS >= 4096) ? 12 : 11;
+    static_assert((1 << LOG_TS) == TS, "table size must be a power of two");
+    constexpr uint32_t EMPTY = 0xffffffffu;
+    __shared__ uint32_t table[TS];
+    __shared__ uint32_t rowcnt[TMAX];
+    __shared__ uint32_t s_special;
+    const int64_t b = blockIdx.x;
+    const int64_t row0 = a.binrow0[b];
+    const int nrows = (int)(a.binrow0[b + 1] - row0);
+    const int64_t toff = a.binoff[b];
+    int N = (int)(a.binoff[b + 1] - toff);
+    if (N > TMAX || nrows > TMAX) {
+        if (threadIdx.x == 0) atomic_or_agent(a.err, (uint32_t)kErrTile);
+        return;
+    }
+    for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
+    for (int x = threadIdx.x; x < nrows; x += BLOCK) rowcnt[x] = 0;
+    if (threadIdx.x == 0) s_special = 0;
+    __syncthreads();
+    const uint32_t *gk = a.keys + toff;
+    const int cb = a.cb;
+    constexpr int IPT = TMAX / BLOCK;
+    uint32_t kr[IPT];
+    // all loads first, so their latencies overlap
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int p = i * BLOCK + threadIdx.x;
+        kr[i] = p < N ? gk[p] : EMPTY;
+    }
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const uint32_t key = kr[i];
+        const int p = i * BLOCK + threadIdx.x;
+        bool fresh = false;
+        if (p < N) {
+            if (key == EMPTY) {  // the one key equal to the empty marker
+                s_special = 1;
+            } else {
+                uint32_t h = (key * 0x9E3779B1u) >> (32 - LOG_TS);
+                while (true) {
+                    const uint32_t old = atomicCAS(&table[h], EMPTY, key);
+                    if (old == EMPTY) {
+                        fresh = true;
+                        break;
+                    }
+                    if (old == key) break;
+                    h = (h + 1) & (TS - 1);
+                }
+            }
+        }
+        // Consecutive lanes hold consecutive tuples, which mostly share a
+        // row: count the fresh keys per run of equal rows within the wave
+        // and let the first lane of each run add the count.
+        const uint32_t row = (p < N && cb < 32) ? (key >> cb) : 0xffffffffu;
+        const uint32_t prev = __shfl_up(row, 1u, kWave);
+        const bool seg_head = (lane == 0) || (row != prev);
+        const uint64_t heads = ballot(seg_head);
+        const uint64_t freshm = ballot(fresh);
+        if (seg_head && row != 0xffffffffu) {
+            const uint64_t above = heads & ~((2ull << lane) - 1);  // heads after this lane
+            const uint32_t end = above ? (uint32_t)__builtin_ctzll(above) : 64u;
+            const uint64_t segm = (end >= 64 ? ~0ull : ((1ull << end) - 1)) & ~((1ull << lane) - 1);
+            const uint32_t cnt = popc64(freshm & segm);
+            if (cnt) atomicAdd(&rowcnt[row], cnt);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_special) rowcnt[cb < 32 ? (EMPTY >> cb) : 0u] += 1;
+    __syncthreads();
+    for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 + x] = rowcnt[x];
+}
+
+// rowptr = exclusive scan of the per-row entry counts (rowptr[m] = nnz(C)).
+struct RowNnzSrc {
+    const uint32_t *rownnz;
+    __device__ uint64_t operator()(int64_t r) const { return rownnz[r]; }
+};
+struct RowPtrDst : NoSide {
+    int64_t *rowptr;
+    int64_t m;
+    __device__ void operator()(int64_t r, uint64_t excl, uint64_t) const { rowptr[r] = (int64_t)excl; }
+    __device__ void total(uint64_t t) const { rowptr[m] = (int64_t)t; }
+};
+
+// ---------------------------------------------------------------------------
+// Sort + compress, one workgroup per bin.  The bin's N <= TMAX tuples (a
+// contiguous row range of the tuple array) are loaded once; keys are ordered
+// in LDS together with 16-bit slot numbers while the values wait in
+// registers; the values are then parked in LDS by slot.  Equal keys are
+// summed in sorted order by the first tuple of each run (Section 3.5's
+// merge) and written at their final place in C, whose row pointers the
+// count pass and the row scan have already produced.
+//
+// Ordering.  Keys are (row in bin) << cb | column.  The default path is a
+// one-pass bucket sort: bucket = (key - min) >> s with NB buckets, counted
+// and scattered with LDS atomics, after which every key finds its place in
+// its (small) bucket by counting the smaller keys there.  Equal keys may
+// land in any order: they are summed together, so only rounding changes.
+// When a bucket holds more than kBucketLimit keys (clustered columns), the
+// bin is ordered instead by a stable LSD radix sort whose per-wave ranks come
+// from ballots.
 struct SortArgs {
-    int64_t nbins, m;
     const int32_t *binrow0;
     const int64_t *binoff;
     const uint32_t *keys;
     const void *vals;
     int cb;
-    uint64_t *status;
-    uint32_t *ticket;
     uint32_t *err;
-    int64_t *rowptr;
+    const int64_t *rowptr;
     int32_t *colidx;
     void *cvals;
     int64_t capacity;
@@ -397,10 +524,15 @@ struct Merge<float> {
     __device__ float result() const { return s + c; }
 };
 
+constexpr uint32_t kBucketLimit = 40;
+
 template <int BLOCK, int TMAX, class VT>
 __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     constexpr int NW = BLOCK / kWave;
     constexpr int IPT = TMAX / BLOCK;
+    constexpr int NB = TMAX / 2;  // buckets of the one-pass path (hist region)
+    constexpr int LOG_NB = (NB >= 4096) ? 12 : (NB >= 2048) ? 11 : (NB >= 1024) ? 10 : 9;
+    static_assert((1 << LOG_NB) == NB, "NB must be a power of two");
     static_assert(NW >= 4, "digit scan uses the first 256 threads");
     static_assert(TMAX <= 65536, "16-bit slots");
     constexpr int OFF_KA = 0;
@@ -408,12 +540,13 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     constexpr int OFF_KB = OFF_SA + 2 * TMAX;
     constexpr int OFF_SB = OFF_KB + 4 * TMAX;
     constexpr int OFF_H = OFF_SB + 2 * TMAX;
-    constexpr int OFF_END = OFF_H + NW * 256 * 4;
+    constexpr int HWORDS = (NW * 256 > NB) ? NW * 256 : NB;
+    constexpr int OFF_END = OFF_H + HWORDS * 4;
     static_assert(OFF_KB + (int)sizeof(VT) * TMAX <= OFF_END, "values must fit the free half");
+    static_assert(NB % BLOCK == 0, "bucket scan: whole buckets per thread");
     __shared__ __align__(16) uint8_t smem[OFF_END];
     __shared__ uint32_t s_wsum[NW];
-    __shared__ int64_t s_bin, s_base;
-    __shared__ uint32_t s_nnzb;
+    __shared__ uint32_t s_red[3 * NW];
 
     uint32_t *keyA = (uint32_t *)(smem + OFF_KA);
     uint16_t *slotA = (uint16_t *)(smem + OFF_SA);
@@ -424,133 +557,225 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
 
     const uint32_t lane = lane_id();
     const uint32_t w = threadIdx.x / kWave;
-    if (threadIdx.x == 0) s_bin = atomic_add_agent(a.ticket, 1u);
-    __syncthreads();
-    const int64_t b = s_bin;
+    const int cb = a.cb;
+    const uint32_t colmask = cb ? ((1u << cb) - 1u) : 0u;
+
+    const int64_t b = blockIdx.x;
     const int64_t row0 = a.binrow0[b];
     const int64_t nrows = a.binrow0[b + 1] - row0;
     const int64_t toff = a.binoff[b];
     int N = (int)(a.binoff[b + 1] - toff);
     if (N > TMAX) {
         if (threadIdx.x == 0) atomic_or_agent(a.err, (uint32_t)kErrTile);
-        N = 0;
+        return;
     }
-    const int cb = a.cb;
-    const VT *gv = (const VT *)a.vals;
-
+    if (N == 0) return;
+    const int64_t base = a.rowptr[row0];
+    const uint32_t *gk = a.keys + toff;
+    const VT *gvb = (const VT *)a.vals + toff;
     uint32_t rk[IPT];
     VT rv[IPT];
+    uint32_t kmin = 0xffffffffu, kmax = 0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         if (p < N) {
-            rk[i] = a.keys[toff + p];
-            rv[i] = gv[toff + p];
+            rk[i] = gk[p];
+            rv[i] = gvb[p];
+            kmin = rk[i] < kmin ? rk[i] : kmin;
+            kmax = rk[i] > kmax ? rk[i] : kmax;
         }
     }
+    for (int x = threadIdx.x; x < NB; x += BLOCK) hist[x] = 0;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t o1 = __shfl_xor(kmin, d, kWave);
+        const uint32_t o2 = __shfl_xor(kmax, d, kWave);
+        kmin = o1 < kmin ? o1 : kmin;
+        kmax = o2 > kmax ? o2 : kmax;
+    }
+    if (lane == 0) {
+        s_red[w] = kmin;
+        s_red[NW + w] = kmax;
+    }
+    __syncthreads();
+    kmin = 0xffffffffu;
+    kmax = 0;
+    for (int ww = 0; ww < NW; ++ww) {
+        kmin = s_red[ww] < kmin ? s_red[ww] : kmin;
+        kmax = s_red[NW + ww] > kmax ? s_red[NW + ww] : kmax;
+    }
+    const uint32_t span = kmax - kmin;
+    const int spanbits = span ? 32 - __clz(span) : 0;
+    const int sh = spanbits > LOG_NB ? spanbits - LOG_NB : 0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+        if (p < N) atomicAdd(&hist[(rk[i] - kmin) >> sh], 1u);
+    }
+    __syncthreads();
+    {
+        constexpr int BPT = NB / BLOCK;
+        uint32_t c[BPT];
+        uint32_t tsum = 0, tmax = 0;
+#pragma unroll
+        for (int x = 0; x < BPT; ++x) {
+            c[x] = hist[threadIdx.x * BPT + x];
+            tsum += c[x];
+            tmax = c[x] > tmax ? c[x] : tmax;
+        }
+        const uint32_t inc = wave_incl_scan_u32(tsum);
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(tmax, d, kWave);
+            tmax = o > tmax ? o : tmax;
+        }
+        if (lane == kWave - 1) s_wsum[w] = inc;
+        if (lane == 0) s_red[2 * NW + w] = tmax;
+        __syncthreads();
+        uint32_t run = inc - tsum;
+        for (uint32_t ww = 0; ww < w; ++ww) run += s_wsum[ww];
+#pragma unroll
+        for (int x = 0; x < BPT; ++x) {
+            hist[threadIdx.x * BPT + x] = run;
+            run += c[x];
+        }
+    }
+    __syncthreads();
+    uint32_t maxbucket = 0;
+    for (int ww = 0; ww < NW; ++ww) maxbucket = s_red[2 * NW + ww] > maxbucket ? s_red[2 * NW + ww] : maxbucket;
 
-    const int rowbits = nrows > 1 ? 32 - __clz((uint32_t)(nrows - 1)) : 0;
-    const int bits = rowbits + cb;
-    const int passes = (bits + 7) / 8;
-    const int dw = passes ? (bits + passes - 1) / passes : 0;
-
-    uint32_t *dk = (passes & 1) ? keyA : keyB;
-    uint16_t *dsl = (passes & 1) ? slotA : slotB;
-    uint32_t *sk = (passes & 1) ? keyB : keyA;
-    uint16_t *ssl = (passes & 1) ? slotB : slotA;
-    if (passes == 0) {
+    if (maxbucket <= kBucketLimit) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
             if (p < N) {
-                keyA[p] = rk[i];
-                slotA[p] = (uint16_t)p;
-            }
-        }
-    }
-    uint32_t *wh = hist + w * 256;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * dw;
-        const int width = (bits - shift) < dw ? (bits - shift) : dw;
-        const uint32_t R = 1u << width;
-        const uint32_t dmask = R - 1;
-        for (uint32_t d = lane; d < R; d += kWave) wh[d] = 0;
-        uint32_t kv[IPT], sv[IPT], rankdig[IPT];
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-            const bool act = p < N;
-            uint32_t key = 0, slot = 0;
-            if (act) {
-                key = pass == 0 ? rk[i] : sk[p];
-                slot = pass == 0 ? (uint32_t)p : (uint32_t)ssl[p];
-            }
-            const uint32_t dig = (key >> shift) & dmask;
-            uint64_t peers = ballot(act);
-            for (int bt = 0; bt < width; ++bt) {
-                const bool bit = (dig >> bt) & 1u;
-                const uint64_t bb = ballot(act && bit);
-                peers &= bit ? bb : ~bb;
-            }
-            uint32_t rank = 0;
-            if (act) {
-                const uint32_t old = wh[dig];
-                rank = old + popc_lt(peers);
-                if (lane == (uint32_t)__builtin_ctzll(peers)) wh[dig] = old + popc64(peers);
-            }
-            kv[i] = key;
-            sv[i] = slot;
-            rankdig[i] = rank | (dig << 16);
-        }
-        __syncthreads();
-        // digit offsets in (digit, wave) order
-        uint32_t tot = 0, inc = 0;
-        if (threadIdx.x < 256) {
-            if (threadIdx.x < R)
-                for (int ww = 0; ww < NW; ++ww) tot += hist[ww * 256 + threadIdx.x];
-            inc = wave_incl_scan_u32(tot);
-            if (lane == kWave - 1) s_wsum[w] = inc;
-        }
-        __syncthreads();
-        if (threadIdx.x < R) {
-            uint32_t run = inc - tot;
-            for (uint32_t ww = 0; ww < w; ++ww) run += s_wsum[ww];
-            for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t h = hist[ww * 256 + threadIdx.x];
-                hist[ww * 256 + threadIdx.x] = run;
-                run += h;
+                const uint32_t pos = atomicAdd(&hist[(rk[i] - kmin) >> sh], 1u);
+                keyB[pos] = rk[i];
+                slotB[pos] = (uint16_t)p;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-            if (p < N) {
-                const uint32_t dig = rankdig[i] >> 16;
-                const uint32_t dest = wh[dig] + (rankdig[i] & 0xffffu);
-                dk[dest] = kv[i];
-                dsl[dest] = (uint16_t)sv[i];
+            const int q = (int)w * kWave * IPT + i * kWave + (int)lane;
+            if (q < N) {
+                const uint32_t key = keyB[q];
+                const uint32_t bk = (key - kmin) >> sh;
+                const uint32_t be = hist[bk];
+                const uint32_t bs = bk ? hist[bk - 1] : 0u;
+                uint32_t rank = bs;
+                for (uint32_t x = bs; x < be; ++x) {
+                    const uint32_t kx = keyB[x];
+                    rank += (kx < key) || (kx == key && x < (uint32_t)q);
+                }
+                keyA[rank] = key;
+                slotA[rank] = slotB[q];
             }
         }
         __syncthreads();
-        uint32_t *tk = sk;
-        sk = dk;
-        dk = tk;
-        uint16_t *ts = ssl;
-        ssl = dsl;
-        dsl = ts;
+    } else {
+        // stable LSD radix sort, per-wave ballot ranking
+        const int rowbits = nrows > 1 ? 32 - __clz((uint32_t)(nrows - 1)) : 0;
+        const int bits = rowbits + cb;
+        const int passes = (bits + 7) / 8;
+        const int dw = passes ? (bits + passes - 1) / passes : 0;
+        uint32_t *dk = (passes & 1) ? keyA : keyB;
+        uint16_t *dsl = (passes & 1) ? slotA : slotB;
+        uint32_t *sk = (passes & 1) ? keyB : keyA;
+        uint16_t *ssl = (passes & 1) ? slotB : slotA;
+        if (passes == 0) {
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+                if (p < N) {
+                    keyA[p] = rk[i];
+                    slotA[p] = (uint16_t)p;
+                }
+            }
+        }
+        uint32_t *wh = hist + w * 256;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int shift = pass * dw;
+            const int width = (bits - shift) < dw ? (bits - shift) : dw;
+            const uint32_t R = 1u << width;
+            const uint32_t dmask = R - 1;
+            __syncthreads();
+            for (uint32_t d = lane; d < R; d += kWave) wh[d] = 0;
+            uint32_t kv[IPT], sv[IPT], rankdig[IPT];
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+                const bool act = p < N;
+                uint32_t key = 0, slot = 0;
+                if (act) {
+                    key = pass == 0 ? rk[i] : sk[p];
+                    slot = pass == 0 ? (uint32_t)p : (uint32_t)ssl[p];
+                }
+                const uint32_t dig = (key >> shift) & dmask;
+                uint64_t peers = ballot(act);
+                for (int bt = 0; bt < width; ++bt) {
+                    const bool bit = (dig >> bt) & 1u;
+                    const uint64_t bb = ballot(act && bit);
+                    peers &= bit ? bb : ~bb;
+                }
+                uint32_t rank = 0;
+                if (act) {
+                    const uint32_t old = wh[dig];
+                    rank = old + popc_lt(peers);
+                    if (lane == (uint32_t)__builtin_ctzll(peers)) wh[dig] = old + popc64(peers);
+                }
+                kv[i] = key;
+                sv[i] = slot;
+                rankdig[i] = rank | (dig << 16);
+            }
+            __syncthreads();
+            uint32_t tot = 0, inc = 0;
+            if (threadIdx.x < 256) {
+                if (threadIdx.x < R)
+                    for (int ww = 0; ww < NW; ++ww) tot += hist[ww * 256 + threadIdx.x];
+                inc = wave_incl_scan_u32(tot);
+                if (lane == kWave - 1) s_wsum[w] = inc;
+            }
+            __syncthreads();
+            if (threadIdx.x < R) {
+                uint32_t run = inc - tot;
+                for (uint32_t ww = 0; ww < w; ++ww) run += s_wsum[ww];
+                for (int ww = 0; ww < NW; ++ww) {
+                    const uint32_t h = hist[ww * 256 + threadIdx.x];
+                    hist[ww * 256 + threadIdx.x] = run;
+                    run += h;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+                if (p < N) {
+                    const uint32_t dig = rankdig[i] >> 16;
+                    const uint32_t dest = wh[dig] + (rankdig[i] & 0xffffu);
+                    dk[dest] = kv[i];
+                    dsl[dest] = (uint16_t)sv[i];
+                }
+            }
+            uint32_t *tk = sk;
+            sk = dk;
+            dk = tk;
+            uint16_t *ts = ssl;
+            ssl = dsl;
+            dsl = ts;
+        }
+        __syncthreads();
     }
-    // sorted keys and slots are in keyA / slotA; park values by slot
+    // park the values by slot, then merge runs of equal keys and write them
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         if (p < N) vl[p] = rv[i];
     }
     __syncthreads();
-
-    // heads of runs of equal keys, ranked in sorted order
-    uint32_t hr[IPT];
     uint32_t wrun = 0;
+    uint32_t hr[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
@@ -562,57 +787,33 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     }
     if (lane == 0) s_wsum[w] = wrun;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t t = s_wsum[ww];
-            s_wsum[ww] = acc;
-            acc += t;
-        }
-        const int64_t base = (int64_t)look_back<SumOp>(a.status, b, (uint64_t)acc, a.err);
-        s_base = base;
-        if (b == a.nbins - 1) a.rowptr[a.m] = base + acc;
-        s_nnzb = acc;
-    }
-    __syncthreads();
-    const int64_t base = s_base;
-    const uint32_t nnzb = s_nnzb;
-    const uint32_t wbase = s_wsum[w];
-    const uint32_t colmask = cb ? ((1u << cb) - 1u) : 0u;
+    uint32_t wbase = 0;
+    for (uint32_t ww = 0; ww < w; ++ww) wbase += s_wsum[ww];
     VT *cv = (VT *)a.cvals;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-        if (p < N && hr[i] != 0xffffffffu) {
+        if (hr[i] != 0xffffffffu) {
+            const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
             const uint32_t key = keyA[p];
-            const int64_t out = base + wbase + hr[i];
             Merge<VT> mg;
             mg.start(vl[slotA[p]]);
             for (int q = p + 1; q < N && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
+            const int64_t out = base + wbase + hr[i];
             if (out < a.capacity) {
                 a.colidx[out] = (int32_t)(key & colmask);
                 cv[out] = mg.result();
             } else {
                 atomic_or_agent(a.err, (uint32_t)kErrCapacity);
             }
-            const int64_t rl = cb < 32 ? (int64_t)(key >> cb) : 0;
-            const int64_t rlprev = p == 0 ? -1 : (cb < 32 ? (int64_t)(keyA[p - 1] >> cb) : 0);
-            for (int64_t rr = rlprev + 1; rr <= rl; ++rr) a.rowptr[row0 + rr] = out;
-        }
-        if (p == N - 1) {
-            const int64_t rl = cb < 32 ? (int64_t)(keyA[p] >> cb) : 0;
-            for (int64_t rr = rl + 1; rr < nrows; ++rr) a.rowptr[row0 + rr] = base + nnzb;
         }
     }
-    if (N == 0)
-        for (int64_t rr = threadIdx.x; rr < nrows; rr += BLOCK) a.rowptr[row0 + rr] = base;
 }
 
-// Streaming copy with 16-byte accesses (bandwidth reference).
+// Streaming copy with 16-byte accesses, one element per thread
+// (bandwidth reference).
 __global__ __launch_bounds__(256) void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n) {
-    int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (; i < n; i += stride) dst[i] = src[i];
+    const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 }  // namespace pb

@@ -44,6 +44,7 @@ pb_status fail(pb_status s, const char *fmt, ...) {
 // Kernel shapes.
 constexpr int kScanBlock = 256, kScanIpt = 8, kScanTile = kScanBlock * kScanIpt;
 constexpr int kSortBlock = 512, kSortTmax = 4096;
+constexpr int kSortBlockSmall = 256, kSortTmaxSmall = 2048;
 constexpr int kExpBlock = 256, kExpWin = 2048;
 constexpr int kDefaultTile = 4096;
 constexpr int kDefaultChunk = 4096;
@@ -137,7 +138,8 @@ struct pb_plan {
     SymInfo *info = nullptr;
     int64_t *F = nullptr;
     uint64_t *R = nullptr;
-    uint64_t *rowinfo = nullptr;
+    RowTab *rowtab = nullptr;
+    uint32_t *runpos = nullptr;
     int32_t *binrow0 = nullptr;
     int64_t *binoff = nullptr;
     // host facts
@@ -154,13 +156,14 @@ struct SymLayout {
     uint64_t *stF, *stR, *stB;
     uint64_t *R;
     int64_t *F;
-    uint64_t *rowinfo;
+    RowTab *rowtab;
+    uint32_t *runpos;
     int32_t *binrow0;
     int64_t *binoff;
     size_t zero_bytes, total;
 };
 
-SymLayout sym_layout(void *base, int64_t m, int64_t k) {
+SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza) {
     Carver cv(base);
     SymLayout L{};
     // zeroed region first
@@ -172,7 +175,8 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k) {
     L.R = cv.take<uint64_t>(m + 1);
     L.zero_bytes = (cv.off + 255) & ~(size_t)255;
     L.F = cv.take<int64_t>(k + 1);
-    L.rowinfo = cv.take<uint64_t>(m);
+    L.rowtab = cv.take<RowTab>(m);
+    L.runpos = cv.take<uint32_t>(nnza);
     L.binrow0 = cv.take<int32_t>(m + 1);
     L.binoff = cv.take<int64_t>(m + 1);
     L.total = (cv.off + 255) & ~(size_t)255;
@@ -181,9 +185,9 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k) {
 
 struct NumLayout {
     uint32_t *ticket, *err;
-    uint32_t *bincur;
     uint64_t *status;
     int32_t *kstart;
+    uint32_t *rownnz;
     uint32_t *keys;
     void *vals;
     size_t zero_bytes, total;
@@ -192,13 +196,12 @@ struct NumLayout {
 NumLayout num_layout(void *base, const pb_plan *p) {
     Carver cv(base);
     NumLayout L{};
-    const int64_t nb = (int64_t)p->h.nbins;
     L.ticket = cv.take<uint32_t>(2);
     L.err = L.ticket + 1;
-    L.bincur = cv.take<uint32_t>(nb);
-    L.status = cv.take<uint64_t>(nb);
+    L.status = cv.take<uint64_t>(ceil_div(p->m, kScanTile) + 1);
     L.zero_bytes = (cv.off + 255) & ~(size_t)255;
     L.kstart = cv.take<int32_t>(p->nchunks + 1);
+    L.rownnz = cv.take<uint32_t>(p->m);
     const int64_t flop = (int64_t)p->h.flop;
     L.keys = cv.take<uint32_t>(flop);
     if (p->prec == PB_F64) L.vals = cv.take<double>(flop);
@@ -226,6 +229,24 @@ pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *t
                        0, st, n, src, dst, status, ticket, err);
     PB_LAUNCHED(name);
     return PB_OK;
+}
+
+// Workgroups of a persistent kernel: as many as fit on the device at once
+// (at most `work`, at least 1).
+unsigned resident_grid(const void *kern, int block, int64_t work) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per <= 0) per = 1;
+    int64_t g = (int64_t)per * cus;
+    if (g > work) g = work;
+    return (unsigned)(g > 0 ? g : 1);
 }
 
 pb_status resolve_tune(const pb_tune *t, int *T, int *chunk) {
@@ -279,18 +300,19 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     int T, chunk;
     if ((s = resolve_tune(tune, &T, &chunk)) != PB_OK) return s;
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
-    const size_t need = sym_layout(nullptr, m, k).total;
+    const size_t need = sym_layout(nullptr, m, k, A->nnz).total;
     if (!sym_ws) {
         *sym_ws_bytes = need;
         return PB_OK;
     }
     if (*sym_ws_bytes < need) return fail(PB_ERR_WORKSPACE, "symbolic workspace has %zu bytes, needs %zu", *sym_ws_bytes, need);
     if (!plan || !flop || !workspace_bytes) return fail(PB_ERR_ARG, "plan/flop/workspace_bytes output is NULL");
+    if (B->nnz >= (int64_t)1 << 32) return fail(PB_ERR_RANGE, "nnz(B) must be below 2^32 (32-bit in-row run offsets)");
     const int cb = col_bits(n);
     if (cb > 31) return fail(PB_ERR_RANGE, "n too large for packed keys");
 
     hipStream_t st = (hipStream_t)hip_stream;
-    SymLayout L = sym_layout(sym_ws, m, k);
+    SymLayout L = sym_layout(sym_ws, m, k, A->nnz);
     pb_plan *p = new pb_plan();
     p->m = m;
     p->k = k;
@@ -304,7 +326,8 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->info = L.info;
     p->F = L.F;
     p->R = L.R;
-    p->rowinfo = L.rowinfo;
+    p->rowtab = L.rowtab;
+    p->runpos = L.runpos;
     p->binrow0 = L.binrow0;
     p->binoff = L.binoff;
 
@@ -318,7 +341,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
                                              &L.tickets[0], &L.info->err, st, "flop scan")) != PB_OK)
                     break;
                 const int64_t grid = ceil_div(k, 256);
-                hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)grid), dim3(256), 0, st, k, A->ptr, A->idx, B->ptr, L.R);
+                hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)grid), dim3(256), 0, st, k, A->ptr, A->idx, B->ptr, L.R, L.runpos);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) { rs = fail(PB_ERR_HIP, "launch rowflop: %s", hipGetErrorString(e)); break; }
             } else {
@@ -330,7 +353,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
                     break;
                 const int rowbits = 32 - cb;
                 if ((rs = launch_scan<BinOp>(m, BinSrc{L.R, L.info, (uint64_t)T, rowbits, nullptr, 0},
-                                             BinDst{L.rowinfo, L.binrow0, L.binoff, L.R, m, (uint64_t)T, L.info},
+                                             BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)T, L.info},
                                              L.stB, &L.tickets[2], &L.info->err, st, "bin scan")) != PB_OK)
                     break;
             }
@@ -396,7 +419,7 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
                            (int64_t)p->chunk, p->k, p->F, L.kstart);
         PB_LAUNCHED("chunk start");
         ExpandArgs ea{flop, p->k, p->F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val,
-                      p->rowinfo, p->binoff, L.bincur, L.keys, L.vals, p->cb, L.err};
+                      p->runpos, p->rowtab, L.keys, L.vals, p->cb, L.err};
         ProfScope ps(st, 1);
         if (p->chunk == 4096) {
             if (p->prec == PB_F64)
@@ -412,13 +435,31 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
         PB_LAUNCHED("expand");
     }
     if (nbins > 0) {
-        SortArgs sa{nbins, p->m, p->binrow0, p->binoff, L.keys, L.vals, p->cb, L.status, L.ticket, L.err,
-                    C->rowptr, C->colidx, C->val, C->capacity};
+        {
+            ProfScope ps(st, 3);
+            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err};
+            if (p->T <= kSortTmaxSmall)
+                hipLaunchKernelGGL((k_row_nnz<512, kSortTmaxSmall>), dim3((unsigned)nbins), dim3(512), 0, st, ca);
+            else
+                hipLaunchKernelGGL((k_row_nnz<512, kSortTmax>), dim3((unsigned)nbins), dim3(512), 0, st, ca);
+            PB_LAUNCHED("row counts");
+            if ((s = launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m}, L.status, L.ticket,
+                                        L.err, st, "row pointer scan")) != PB_OK)
+                return s;
+        }
+        SortArgs sa{p->binrow0, p->binoff, L.keys, L.vals, p->cb, L.err, C->rowptr, C->colidx, C->val, C->capacity};
         ProfScope ps(st, 2);
-        if (p->prec == PB_F64)
-            hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins), dim3(kSortBlock), 0, st, sa);
-        else
-            hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins), dim3(kSortBlock), 0, st, sa);
+        if (p->T <= kSortTmaxSmall) {
+            if (p->prec == PB_F64)
+                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins), dim3(kSortBlockSmall), 0, st, sa);
+            else
+                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins), dim3(kSortBlockSmall), 0, st, sa);
+        } else {
+            if (p->prec == PB_F64)
+                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins), dim3(kSortBlock), 0, st, sa);
+            else
+                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins), dim3(kSortBlock), 0, st, sa);
+        }
         PB_LAUNCHED("sort+compress");
     }
     if (nnzC) {
@@ -488,8 +529,8 @@ pb_status spgemm_copy(void *dst, const void *src, size_t bytes, void *hip_stream
     if ((bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15)) return fail(PB_ERR_ARG, "16-byte alignment required");
     const int64_t n = (int64_t)(bytes / 16);
     if (n == 0) return PB_OK;
-    int64_t grid = ceil_div(n, 256 * 4);
-    if (grid > 256 * 64) grid = 256 * 64;
+    const int64_t grid = ceil_div(n, 256);
+    if (grid > 0x7fffffffll) return fail(PB_ERR_RANGE, "copy too large");
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)hip_stream, (uint4 *)dst, (const uint4 *)src, n);
     PB_LAUNCHED("copy");
     return PB_OK;
