@@ -84,8 +84,8 @@ typedef struct {
 } pb_csr_out;
 
 /* Tuning knobs; 0 selects the default.
- *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 1024..8192
- *   expand_chunk  tuples per expand workgroup: 1024..16384, multiple of 256 */
+ *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096
+ *   expand_chunk  tuples per expand wave: 512, 1024 or 2048 */
 typedef struct {
     int32_t tile_tuples;
     int32_t expand_chunk;
@@ -141,6 +141,33 @@ pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision
 pb_status spgemm_numeric(pb_plan *plan, const pb_csx *A_csc, const pb_csx *B_csr,
                          void *workspace, size_t workspace_bytes, pb_csr_out *C,
                          int64_t *nnzC, void *hip_stream);
+
+/*
+ * Batched products C_i = A_i * B_i, i < count, of uneven sizes (a workload
+ * beyond the paper).  The batch runs as one block-diagonal product: the
+ * problems' rows and inner indices are laid side by side, bins never span
+ * two problems, and every kernel of the path is launched once for the whole
+ * batch.  A_csc / B_csr / C are arrays of `count` descriptors.
+ *
+ * spgemm_batched_symbolic: as spgemm_symbolic (size query with
+ * sym_ws == NULL; one stream sync otherwise); `flop` is a host array of
+ * `count` entries that receives each problem's multiplication count (the
+ * capacity that always fits its C).  The symbolic workspace also holds a
+ * packed copy of the inputs' structure.
+ *
+ * spgemm_batched: the numeric step for the whole batch.  C[i].rowptr gets
+ * A_i.nrows+1 entries.  With nnzC == NULL nothing synchronises and the call
+ * only enqueues work on hip_stream (descriptor uploads from pinned memory
+ * owned by the plan, then kernels), so it can be captured in a hipGraph and
+ * replayed while the plan and the descriptor arrays' contents are unchanged;
+ * otherwise nnzC is a host array of `count` entries (PB_ERR_CAPACITY names
+ * the first problem whose capacity was too small).
+ */
+pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A_csc, const pb_csx *B_csr, pb_precision prec,
+                                  const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes, void *hip_stream,
+                                  pb_plan **plan, int64_t *flop, size_t *workspace_bytes);
+pb_status spgemm_batched(pb_plan *plan, int32_t count, const pb_csx *A_csc, const pb_csx *B_csr, void *workspace,
+                         size_t workspace_bytes, pb_csr_out *C, int64_t *nnzC, void *hip_stream);
 
 /* Copy the plan's facts to *info. */
 pb_status spgemm_plan_info(const pb_plan *plan, pb_plan_info *info);

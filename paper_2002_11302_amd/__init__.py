@@ -18,7 +18,7 @@ __all__ = [
     "DeviceCsx", "DeviceCsr", "Plan", "PbError", "PHASES",
     "spgemm_symbolic", "spgemm_numeric", "spgemm_plan_info", "spgemm_plan_destroy",
     "spgemm_status_string", "spgemm_last_error", "spgemm_profile_begin", "spgemm_profile_end",
-    "spgemm_copy", "spgemm", "load",
+    "spgemm_copy", "spgemm", "load", "BatchPlan", "spgemm_batched_symbolic", "spgemm_batched", "spgemm_batch",
 ]
 
 
@@ -219,3 +219,81 @@ def spgemm(A: DeviceCsx, B: DeviceCsx, precision: str = "f64", tune: dict | None
     finally:
         plan.close()
     return DeviceCsr(A.nrows, B.ncols, rowptr, colidx[:nnz], val[:nnz])
+
+
+# ---------------------------------------------------------------- batches
+class BatchPlan(Plan):
+    """Plan of a batch; ``flops[i]`` is problem i's multiplication count."""
+
+    def __init__(self, handle: int, sym_ws, flops, ws_bytes: int, precision: str):
+        super().__init__(handle, sym_ws, int(sum(flops)), ws_bytes, precision)
+        self.flops = list(flops)
+        self.count = len(self.flops)
+
+
+def _abi_array(mats):
+    arr = (_b.PbCsx * len(mats))()
+    for i, x in enumerate(mats):
+        arr[i] = x._abi()
+    return arr
+
+
+def spgemm_batched_symbolic(pairs, precision: str = "f64", tune: dict | None = None, sym_ws=None, stream=None):
+    """Symbolic step for a batch of (A_csc, B_csr) pairs.  With
+    ``sym_ws=None`` returns the workspace size (query); else a BatchPlan."""
+    lib = _b.lib()
+    count = len(pairs)
+    aa = _abi_array([a for a, _ in pairs])
+    bb = _abi_array([b for _, b in pairs])
+    prec = _b.PRECISIONS[precision]
+    nbytes = ctypes.c_size_t(0)
+    if sym_ws is None:
+        _b.check(lib.spgemm_batched_symbolic(count, aa, bb, prec, _tune(tune), None, ctypes.byref(nbytes), None, None,
+                                             None, None), "spgemm_batched_symbolic(query)")
+        return int(nbytes.value)
+    nbytes.value = sym_ws.numel() * sym_ws.element_size()
+    plan = ctypes.c_void_p()
+    flops = (ctypes.c_int64 * count)()
+    wsb = ctypes.c_size_t()
+    _b.check(lib.spgemm_batched_symbolic(count, aa, bb, prec, _tune(tune), sym_ws.data_ptr(), ctypes.byref(nbytes),
+                                         _stream(stream), ctypes.byref(plan), flops, ctypes.byref(wsb)),
+             "spgemm_batched_symbolic")
+    return BatchPlan(plan.value, sym_ws, [int(f) for f in flops], int(wsb.value), precision)
+
+
+def spgemm_batched(plan: BatchPlan, pairs, workspace, outs, sync: bool = True, stream=None):
+    """Numeric step for the whole batch.  ``outs[i] = (rowptr, colidx, val)``
+    device tensors.  Returns the list of nnz(C_i) when ``sync``; with
+    ``sync=False`` only enqueues work (capturable in a HIP graph)."""
+    lib = _b.lib()
+    count = len(pairs)
+    aa = _abi_array([a for a, _ in pairs])
+    bb = _abi_array([b for _, b in pairs])
+    cc = (_b.PbCsrOut * count)()
+    for i, (rp, ci, cv) in enumerate(outs):
+        cap = int(ci.numel())
+        cc[i] = _b.PbCsrOut(rp.data_ptr(), ci.data_ptr() if cap else None, cv.data_ptr() if cap else None, cap)
+    nnz = (ctypes.c_int64 * count)()
+    wsp = workspace.data_ptr() if workspace is not None and workspace.numel() else None
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _b.check(lib.spgemm_batched(plan.handle, count, aa, bb, wsp, wsb, cc, nnz if sync else None, _stream(stream)),
+             "spgemm_batched")
+    return [int(x) for x in nnz] if sync else None
+
+
+def spgemm_batch(pairs, precision: str = "f64", tune: dict | None = None, stream=None):
+    """C_i = A_i * B_i for a list of (A_csc, B_csr) pairs, as one batch."""
+    torch = _torch()
+    dev = pairs[0][0].ptr.device
+    nsym = spgemm_batched_symbolic(pairs, precision, tune)
+    plan = spgemm_batched_symbolic(pairs, precision, tune, sym_ws=_alloc_bytes(nsym, dev), stream=stream)
+    try:
+        ws = _alloc_bytes(plan.workspace_bytes, dev)
+        vdt = torch.float64 if precision == "f64" else torch.float32
+        outs = [(torch.empty(a.nrows + 1, dtype=torch.int64, device=dev),
+                 torch.empty(max(f, 1), dtype=torch.int32, device=dev),
+                 torch.empty(max(f, 1), dtype=vdt, device=dev)) for (a, _), f in zip(pairs, plan.flops)]
+        nnz = spgemm_batched(plan, pairs, ws, outs, sync=True, stream=stream)
+    finally:
+        plan.close()
+    return [DeviceCsr(a.nrows, b.ncols, rp, ci[:z], cv[:z]) for (a, b), (rp, ci, cv), z in zip(pairs, outs, nnz)]

@@ -76,6 +76,11 @@ SIGNATURES = {
     "spgemm_profile_begin": (ctypes.c_int, []),
     "spgemm_profile_end": (ctypes.c_int, [ctypes.POINTER(PbProfile)]),
     "spgemm_copy": (ctypes.c_int, [_vp, _vp, _sz, _vp]),
+    "spgemm_batched_symbolic": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx), ctypes.c_int,
+                                               ctypes.POINTER(PbTune), _vp, ctypes.POINTER(_sz), _vp, ctypes.POINTER(_vp),
+                                               ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
+    "spgemm_batched": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx), _vp, _sz,
+                                      ctypes.POINTER(PbCsrOut), ctypes.POINTER(_i64), _vp]),
 }
 
 _lib = None

@@ -308,59 +308,78 @@ __device__ __forceinline__ void divmod_u(int64_t x, int64_t d, int64_t &q, int64
     }
 }
 
-template <int BLOCK, int IPT, int WMAX, class VT>
-__global__ __launch_bounds__(BLOCK) void k_expand(ExpandArgs a) {
-    constexpr int C = BLOCK * IPT;
-    __shared__ int64_t s_F[WMAX];
-    const int64_t c = blockIdx.x;
-    const int64_t t0 = c * (int64_t)C;
-    const int64_t t1 = (t0 + C < a.flop) ? t0 + C : a.flop;
-    const int64_t k0 = a.kstart[c];
-    const int64_t kl = a.kstart[c + 1];
-    const int64_t nwin = kl - k0 + 2;  // F[k0 .. kl+1]
-    const bool windowed = nwin <= WMAX;
-    if (windowed)
-        for (int64_t i = threadIdx.x; i < nwin; i += BLOCK) s_F[i] = a.F[k0 + i];
-    __syncthreads();
-
+// One wave per chunk of W tuples.  The wave walks the columns its chunk
+// touches; the column's facts (F[k], where A(:,k) and B(k,:) start, nnz of
+// B(k,:)) are wave-uniform, and each lane takes one tuple of the current
+// 64-tuple step: (i, j) = divmod(t - F[k], nnz(B(k,:))).
+template <int W, class VT>
+__global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
+    const uint32_t lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wave >= nchunks) return;
+    const int64_t t0 = wave * (int64_t)W;
+    const int64_t t1 = (t0 + W < a.flop) ? t0 + W : a.flop;
+    int64_t k = a.kstart[wave];
+    int64_t t = t0;
     VT *vals = (VT *)a.vals;
-    int64_t kw = 0;  // current column relative to k0 (windowed path)
-#pragma unroll 4
-    for (int it = 0; it < IPT; ++it) {
-        const int64_t t = t0 + it * BLOCK + threadIdx.x;
-        if (t >= t1) break;
-        int64_t k, Fk;
-        if (windowed) {
-            // items of a thread ascend: advance from the previous column
-            int steps = 0;
-            while (s_F[kw + 1] <= t && steps < 8) {
-                ++kw;
-                ++steps;
-            }
-            if (s_F[kw + 1] <= t) kw = last_le(s_F, kw, nwin - 1, t);
-            k = k0 + kw;
-            Fk = s_F[kw];
-        } else {
-            k = last_le(a.F, k0, kl + 1, t);
-            Fk = a.F[k];
+    while (t < t1) {
+        const int64_t Fk1 = a.F[k + 1];
+        if (Fk1 <= t) {  // column with no tuples left in this chunk
+            ++k;
+            continue;
         }
+        const int64_t Fk = a.F[k];
         const int64_t bs = a.brp[k];
         const int64_t nb = a.brp[k + 1] - bs;
-        int64_t i, j;
-        divmod_u(t - Fk, nb, i, j);
-        const int64_t e = a.acp[k] + i;
-        const int32_t r = a.ari[e];
-        const RowTab rt = a.rowtab[r];
-        const int64_t slot = rt.base + (int64_t)a.runpos[e] + j;
-        const int64_t q = bs + j;
-        const uint32_t key = (rt.rl << a.cb) | (uint32_t)a.bci[q];
-        const double prod = a.av[e] * a.bv[q];
-        if (slot < a.flop) {
-            a.keys[slot] = key;
-            vals[slot] = (VT)prod;
-        } else {
-            atomic_or_agent(a.err, (uint32_t)kErrBinOverflow);
+        const int64_t as = a.acp[k];
+        const int64_t seg_end = Fk1 < t1 ? Fk1 : t1;
+        // four 64-tuple steps per iteration, every load issued before use
+        constexpr int U = 4;
+        for (int64_t tt = t; tt < seg_end; tt += U * kWave) {
+            int64_t e[U], q[U], jj[U];
+            int32_t r[U];
+            bool on[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t my = tt + u * kWave + lane;
+                on[u] = my < seg_end;
+                int64_t i = 0, j = 0;
+                if (on[u]) divmod_u(my - Fk, nb, i, j);
+                e[u] = as + i;
+                q[u] = bs + j;
+                jj[u] = j;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = on[u] ? a.ari[e[u]] : 0;
+            uint32_t rp[U], col[U];
+            double av[U], bvv[U];
+            RowTab rt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (on[u]) {
+                    rp[u] = a.runpos[e[u]];
+                    av[u] = a.av[e[u]];
+                    col[u] = (uint32_t)a.bci[q[u]];
+                    bvv[u] = a.bv[q[u]];
+                    rt[u] = a.rowtab[r[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (on[u]) {
+                    const int64_t slot = rt[u].base + (int64_t)rp[u] + jj[u];
+                    const uint32_t key = (rt[u].rl << a.cb) | col[u];
+                    if (slot < a.flop) {
+                        a.keys[slot] = key;
+                        vals[slot] = (VT)(av[u] * bvv[u]);
+                    } else {
+                        atomic_or_agent(a.err, (uint32_t)kErrBinOverflow);
+                    }
+                }
+            }
         }
+        t = seg_end;
+        ++k;
     }
 }
 
@@ -468,6 +487,93 @@ struct RowPtrDst : NoSide {
 };
 
 // ---------------------------------------------------------------------------
+// Batched products.  A batch C_i = A_i * B_i is run as one block-diagonal
+// product: A_i's columns and rows and B_i's rows are laid side by side
+// (row and inner indices offset, B's column indices kept local because bins
+// never span two problems), and every problem's C goes to its own arrays.
+struct ProbDesc {
+    const int64_t *aptr;
+    const int32_t *aidx;
+    const double *aval;
+    const int64_t *bptr;
+    const int32_t *bidx;
+    const double *bval;
+    int64_t m, k, n, nnza, nnzb;
+    int64_t mbase, kbase, abase, bbase;
+};
+struct OutDesc {
+    int64_t *rowptr;
+    int32_t *colidx;
+    void *val;
+    int64_t capacity;
+    int64_t row0;  // first row of the problem in the block-diagonal product
+    int64_t m;
+};
+
+// what: bit 0 = pointers and indices, bit 1 = values.  Problem i = blockIdx.y.
+__global__ __launch_bounds__(256) void k_pack(const ProbDesc *pd, int count, int what, int64_t *acp, int32_t *ari,
+                                              double *av, int64_t *brp, int32_t *bci, double *bv) {
+    const ProbDesc d = pd[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t x0 = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (what & 1) {
+        for (int64_t x = x0; x < d.k; x += stride) {
+            acp[d.kbase + x] = d.aptr[x] + d.abase;
+            brp[d.kbase + x] = d.bptr[x] + d.bbase;
+        }
+        for (int64_t x = x0; x < d.nnza; x += stride) ari[d.abase + x] = d.aidx[x] + (int32_t)d.mbase;
+        for (int64_t x = x0; x < d.nnzb; x += stride) bci[d.bbase + x] = d.bidx[x];
+        if ((int)blockIdx.y == count - 1 && x0 == 0) {
+            acp[d.kbase + d.k] = d.abase + d.nnza;
+            brp[d.kbase + d.k] = d.bbase + d.nnzb;
+        }
+    }
+    if (what & 2) {
+        for (int64_t x = x0; x < d.nnza; x += stride) av[d.abase + x] = d.aval[x];
+        for (int64_t x = x0; x < d.nnzb; x += stride) bv[d.bbase + x] = d.bval[x];
+    }
+}
+
+// problem holding global row r (problems sorted by first row; empty
+// problems share their successor's first row and are skipped)
+__device__ __forceinline__ int prob_of_row(const int64_t *prob_row0, int nprob, int64_t r) {
+    return (int)last_le(prob_row0, 0, nprob, r);
+}
+
+// Segmented exclusive scan of entries per row, restarting at every
+// problem's first row; payload bit 61 = segment start, bits 0..60 = sum.
+struct SegSumOp {
+    static __device__ __forceinline__ uint64_t identity() { return 0; }
+    static __device__ __forceinline__ uint64_t combine(uint64_t a, uint64_t b) {
+        constexpr uint64_t F = 1ull << 61;
+        return (b & F) ? ((a & F) | b) : (((a | b) & F) | (((a & ~F) + (b & ~F)) & ~F));
+    }
+};
+struct SegRowNnzSrc {
+    const uint32_t *rownnz;
+    const int64_t *prob_row0;
+    int nprob;
+    __device__ uint64_t operator()(int64_t r) const {
+        const int i = prob_of_row(prob_row0, nprob, r);
+        return ((prob_row0[i] == r) ? (1ull << 61) : 0ull) | (uint64_t)rownnz[r];
+    }
+};
+struct SegRowPtrDst : NoSide {
+    const OutDesc *outs;
+    const int64_t *prob_row0;
+    int nprob;
+    __device__ void operator()(int64_t r, uint64_t excl, uint64_t e) const {
+        constexpr uint64_t F = 1ull << 61;
+        const int i = prob_of_row(prob_row0, nprob, r);
+        const OutDesc od = outs[i];
+        const int64_t before = (e & F) ? 0 : (int64_t)(excl & ~F);
+        od.rowptr[r - od.row0] = before;
+        if (r - od.row0 == od.m - 1) od.rowptr[od.m] = before + (int64_t)(e & ~F);
+    }
+    __device__ void total(uint64_t) const {}
+};
+
+// ---------------------------------------------------------------------------
 // Sort + compress, one workgroup per bin.  The bin's N <= TMAX tuples (a
 // contiguous row range of the tuple array) are loaded once; keys are ordered
 // in LDS together with 16-bit slot numbers while the values wait in
@@ -495,6 +601,10 @@ struct SortArgs {
     int32_t *colidx;
     void *cvals;
     int64_t capacity;
+    // batched: per-problem outputs (null for a single product)
+    const OutDesc *outs;
+    const int64_t *prob_row0;
+    int nprob;
 };
 
 template <class VT>
@@ -570,7 +680,19 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         return;
     }
     if (N == 0) return;
-    const int64_t base = a.rowptr[row0];
+    int64_t base;
+    int32_t *colidx = a.colidx;
+    void *cvals = a.cvals;
+    int64_t capacity = a.capacity;
+    if (a.outs) {
+        const OutDesc od = a.outs[prob_of_row(a.prob_row0, a.nprob, row0)];
+        base = od.rowptr[row0 - od.row0];
+        colidx = od.colidx;
+        cvals = od.val;
+        capacity = od.capacity;
+    } else {
+        base = a.rowptr[row0];
+    }
     const uint32_t *gk = a.keys + toff;
     const VT *gvb = (const VT *)a.vals + toff;
     uint32_t rk[IPT];
@@ -789,7 +911,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     __syncthreads();
     uint32_t wbase = 0;
     for (uint32_t ww = 0; ww < w; ++ww) wbase += s_wsum[ww];
-    VT *cv = (VT *)a.cvals;
+    VT *cv = (VT *)cvals;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         if (hr[i] != 0xffffffffu) {
@@ -799,8 +921,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
             mg.start(vl[slotA[p]]);
             for (int q = p + 1; q < N && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
             const int64_t out = base + wbase + hr[i];
-            if (out < a.capacity) {
-                a.colidx[out] = (int32_t)(key & colmask);
+            if (out < capacity) {
+                colidx[out] = (int32_t)(key & colmask);
                 cv[out] = mg.result();
             } else {
                 atomic_or_agent(a.err, (uint32_t)kErrCapacity);

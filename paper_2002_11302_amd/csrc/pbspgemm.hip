@@ -1,9 +1,10 @@
 // Host runtime of the PB-SpGEMM library: C ABI, validation, workspace
-// layout, kernel launches.  See include/pbspgemm.h for the contract.
+// layout, kernel launches.  The contract is in include/pbspgemm.h.
 #include "pbspgemm.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,13 +42,19 @@ pb_status fail(pb_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(PB_ERR_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
     } while (0)
 
+#define PB_TRY(expr)                \
+    do {                            \
+        pb_status s_ = (expr);      \
+        if (s_ != PB_OK) return s_; \
+    } while (0)
+
 // Kernel shapes.
 constexpr int kScanBlock = 256, kScanIpt = 8, kScanTile = kScanBlock * kScanIpt;
 constexpr int kSortBlock = 512, kSortTmax = 4096;
 constexpr int kSortBlockSmall = 256, kSortTmaxSmall = 2048;
-constexpr int kExpBlock = 256, kExpWin = 2048;
+constexpr int kCountBlock = 512;
 constexpr int kDefaultTile = 4096;
-constexpr int kDefaultChunk = 4096;
+constexpr int kDefaultChunk = 1024;
 
 constexpr int64_t kMaxDim = (1ll << 31) - 1;
 constexpr int64_t kMaxCount = (1ll << 62) - 1;
@@ -66,6 +73,7 @@ struct Carver {
         off += (size_t)(count > 0 ? count : 0) * sizeof(T);
         return p;
     }
+    size_t mark() const { return (off + 255) & ~(size_t)255; }
 };
 
 // ---- profiling -----------------------------------------------------------
@@ -111,14 +119,13 @@ struct ProfScope {
     }
 };
 
-pb_status check_csx(const pb_csx *x, const char *name, bool csc) {
+pb_status check_csx(const pb_csx *x, const char *name) {
     if (!x) return fail(PB_ERR_ARG, "%s is NULL", name);
     if (x->nrows < 0 || x->ncols < 0 || x->nnz < 0) return fail(PB_ERR_SHAPE, "%s has a negative size", name);
     if (x->nrows > kMaxDim || x->ncols > kMaxDim) return fail(PB_ERR_RANGE, "%s dimension exceeds 2^31-1", name);
     if (x->nnz > kMaxCount) return fail(PB_ERR_RANGE, "%s nnz exceeds 2^62", name);
     if (!x->ptr) return fail(PB_ERR_ARG, "%s.ptr is NULL", name);
     if (x->nnz > 0 && (!x->idx || !x->val)) return fail(PB_ERR_ARG, "%s.idx/val is NULL with nnz > 0", name);
-    (void)csc;
     return PB_OK;
 }
 
@@ -127,11 +134,31 @@ int col_bits(int64_t n) {
     return 64 - __builtin_clzll((uint64_t)(n - 1));
 }
 
+pb_status resolve_tune(const pb_tune *t, int *T, int *chunk) {
+    *T = kDefaultTile;
+    *chunk = kDefaultChunk;
+    if (!t) return PB_OK;
+    if (t->tile_tuples) {
+        if (t->tile_tuples < 256 || t->tile_tuples > kSortTmax)
+            return fail(PB_ERR_ARG, "tile_tuples must be in [256, %d]", kSortTmax);
+        *T = t->tile_tuples;
+    }
+    if (t->expand_chunk) {
+        if (t->expand_chunk != 512 && t->expand_chunk != 1024 && t->expand_chunk != 2048)
+            return fail(PB_ERR_ARG, "expand_chunk must be 512, 1024 or 2048");
+        *chunk = t->expand_chunk;
+    }
+    return PB_OK;
+}
+
 }  // namespace
 
 // ---- plan ----------------------------------------------------------------
 struct pb_plan {
+    // the (block-diagonal, for a batch) product: C is m x n, inner dimension k
     int64_t m = 0, k = 0, n = 0, nnzA = 0, nnzB = 0;
+    int32_t count = 1;  // problems in the device tables (1 for a single product)
+    int32_t user_count = 1;
     pb_precision prec = PB_F64;
     int T = kDefaultTile, chunk = kDefaultChunk, cb = 0;
     // symbolic workspace tables
@@ -142,10 +169,23 @@ struct pb_plan {
     uint32_t *runpos = nullptr;
     int32_t *binrow0 = nullptr;
     int64_t *binoff = nullptr;
+    // batch: packed inputs and problem tables (in the symbolic workspace)
+    ProbDesc *pdesc = nullptr;
+    int64_t *prob_row0 = nullptr;
+    int64_t *acp = nullptr, *brp = nullptr;
+    int32_t *ari = nullptr, *bci = nullptr;
+    double *av = nullptr, *bv = nullptr;
+    std::vector<ProbDesc> hdesc;     // host copy (shapes and bases)
+    std::vector<int64_t> prob_flop;  // per-problem multiplications
+    void *pinned = nullptr;          // host staging for descriptor uploads
+    size_t pinned_bytes = 0;
     // host facts
     SymInfo h{};
     int64_t nchunks = 0;
     size_t ws_bytes = 0;
+    ~pb_plan() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
 };
 
 namespace {
@@ -160,10 +200,16 @@ struct SymLayout {
     uint32_t *runpos;
     int32_t *binrow0;
     int64_t *binoff;
+    // batch only
+    ProbDesc *pdesc;
+    int64_t *prob_row0;
+    int64_t *acp, *brp;
+    int32_t *ari, *bci;
+    double *av, *bv;
     size_t zero_bytes, total;
 };
 
-SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza) {
+SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnzb, int32_t count) {
     Carver cv(base);
     SymLayout L{};
     // zeroed region first
@@ -173,13 +219,23 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza) {
     L.stR = cv.take<uint64_t>(ceil_div(m, kScanTile) + 1);
     L.stB = cv.take<uint64_t>(ceil_div(m, kScanTile) + 1);
     L.R = cv.take<uint64_t>(m + 1);
-    L.zero_bytes = (cv.off + 255) & ~(size_t)255;
+    L.zero_bytes = cv.mark();
     L.F = cv.take<int64_t>(k + 1);
     L.rowtab = cv.take<RowTab>(m);
     L.runpos = cv.take<uint32_t>(nnza);
     L.binrow0 = cv.take<int32_t>(m + 1);
     L.binoff = cv.take<int64_t>(m + 1);
-    L.total = (cv.off + 255) & ~(size_t)255;
+    if (count > 1) {
+        L.pdesc = cv.take<ProbDesc>(count);
+        L.prob_row0 = cv.take<int64_t>(count);
+        L.acp = cv.take<int64_t>(k + 1);
+        L.brp = cv.take<int64_t>(k + 1);
+        L.ari = cv.take<int32_t>(nnza);
+        L.bci = cv.take<int32_t>(nnzb);
+        L.av = cv.take<double>(nnza);
+        L.bv = cv.take<double>(nnzb);
+    }
+    L.total = cv.mark();
     return L;
 }
 
@@ -188,6 +244,7 @@ struct NumLayout {
     uint64_t *status;
     int32_t *kstart;
     uint32_t *rownnz;
+    OutDesc *outs;
     uint32_t *keys;
     void *vals;
     size_t zero_bytes, total;
@@ -199,14 +256,15 @@ NumLayout num_layout(void *base, const pb_plan *p) {
     L.ticket = cv.take<uint32_t>(2);
     L.err = L.ticket + 1;
     L.status = cv.take<uint64_t>(ceil_div(p->m, kScanTile) + 1);
-    L.zero_bytes = (cv.off + 255) & ~(size_t)255;
+    L.zero_bytes = cv.mark();
     L.kstart = cv.take<int32_t>(p->nchunks + 1);
     L.rownnz = cv.take<uint32_t>(p->m);
+    L.outs = p->count > 1 ? cv.take<OutDesc>(p->count) : nullptr;
     const int64_t flop = (int64_t)p->h.flop;
     L.keys = cv.take<uint32_t>(flop);
     if (p->prec == PB_F64) L.vals = cv.take<double>(flop);
     else L.vals = cv.take<float>(flop);
-    L.total = (cv.off + 255) & ~(size_t)255;
+    L.total = cv.mark();
     return L;
 }
 
@@ -221,8 +279,8 @@ pb_status fill_zero(void *p, size_t bytes, hipStream_t st) {
 }
 
 template <class Op, class Src, class Dst>
-pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *ticket, uint32_t *err,
-                      hipStream_t st, const char *name) {
+pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *ticket, uint32_t *err, hipStream_t st,
+                      const char *name) {
     if (n <= 0) return PB_OK;
     const int64_t tiles = ceil_div(n, kScanTile);
     hipLaunchKernelGGL((k_chained_scan<kScanBlock, kScanIpt, Op, Src, Dst>), dim3((unsigned)tiles), dim3(kScanBlock),
@@ -231,38 +289,208 @@ pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *t
     return PB_OK;
 }
 
-// Workgroups of a persistent kernel: as many as fit on the device at once
-// (at most `work`, at least 1).
-unsigned resident_grid(const void *kern, int block, int64_t work) {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
+// Symbolic kernels on device arrays (the product's, or the packed batch's):
+// flop scan, per-row flop with run offsets, row scan, bin cut.
+pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const int32_t *ari, const int64_t *brp,
+                       hipStream_t st) {
+    const int64_t m = p->m, k = p->k;
+    if (k > 0) {
+        PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp}, ColFlopDst{{}, L.F, k, L.info}, L.stF, &L.tickets[0],
+                                  &L.info->err, st, "flop scan"));
+        hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp, L.R,
+                           L.runpos);
+        PB_LAUNCHED("rowflop");
+    } else {
+        PB_TRY(fill_zero(L.F, sizeof(int64_t), st));
     }
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per <= 0) per = 1;
-    int64_t g = (int64_t)per * cus;
-    if (g > work) g = work;
-    return (unsigned)(g > 0 ? g : 1);
+    if (m > 0) {
+        PB_TRY(launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(p->T / 2), L.info}, L.stR,
+                                  &L.tickets[1], &L.info->err, st, "row scan"));
+        PB_TRY(launch_scan<BinOp>(
+            m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count},
+            BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info}, L.stB, &L.tickets[2], &L.info->err, st,
+            "bin scan"));
+    }
+    return PB_OK;
 }
 
-pb_status resolve_tune(const pb_tune *t, int *T, int *chunk) {
-    *T = kDefaultTile;
-    *chunk = kDefaultChunk;
-    if (!t) return PB_OK;
-    if (t->tile_tuples) {
-        if (t->tile_tuples < 256 || t->tile_tuples > kSortTmax)
-            return fail(PB_ERR_ARG, "tile_tuples must be in [256, %d]", kSortTmax);
-        *T = t->tile_tuples;
+pb_status finish_symbolic(pb_plan *p, hipStream_t st) {
+    PB_HIP(hipMemcpyAsync(&p->h, p->info, sizeof(SymInfo), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    if (p->h.err) return fail(PB_ERR_INTERNAL, "symbolic device error 0x%x", p->h.err);
+    if (p->m == 0) p->h.nbins = 0;
+    if (p->h.noversize)
+        return fail(PB_ERR_UNSUPPORTED,
+                    "%llu rows expand to more than %d tuples (largest %lld); bins larger than the LDS tile are not "
+                    "supported",
+                    (unsigned long long)p->h.noversize, p->T, (long long)p->h.maxrow);
+    p->nchunks = ceil_div((int64_t)p->h.flop, p->chunk);
+    p->ws_bytes = num_layout(nullptr, p).total;
+    return PB_OK;
+}
+
+// Numeric kernels: expand, entries per row, row pointers, sort+compress.
+// For a single product `C` is its output; for a batch L.outs holds them.
+pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const int32_t *ari, const double *av,
+                      const int64_t *brp, const int32_t *bci, const double *bv, const pb_csr_out *C, hipStream_t st) {
+    const int64_t flop = (int64_t)p->h.flop;
+    const int64_t nbins = (int64_t)p->h.nbins;
+    const bool batch = p->count > 1;
+    const bool f64 = p->prec == PB_F64;
+    if (flop > 0) {
+        hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(p->nchunks + 1, 256)), dim3(256), 0, st, p->nchunks,
+                           (int64_t)p->chunk, p->k, p->F, L.kstart);
+        PB_LAUNCHED("chunk start");
+        ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, ari, av, brp, bci, bv, p->runpos, p->rowtab, L.keys, L.vals,
+                      p->cb, L.err};
+        ProfScope ps(st, 1);
+        const unsigned grid = (unsigned)ceil_div(p->nchunks, 4);
+        switch (p->chunk) {
+            case 512:
+                if (f64) hipLaunchKernelGGL((k_expand<512, double>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                else hipLaunchKernelGGL((k_expand<512, float>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                break;
+            case 2048:
+                if (f64) hipLaunchKernelGGL((k_expand<2048, double>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                else hipLaunchKernelGGL((k_expand<2048, float>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                break;
+            default:
+                if (f64) hipLaunchKernelGGL((k_expand<1024, double>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                else hipLaunchKernelGGL((k_expand<1024, float>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                break;
+        }
+        PB_LAUNCHED("expand");
     }
-    if (t->expand_chunk) {
-        if (t->expand_chunk != 2048 && t->expand_chunk != 4096)
-            return fail(PB_ERR_ARG, "expand_chunk must be 2048 or 4096");
-        *chunk = t->expand_chunk;
+    if (nbins > 0) {
+        {
+            ProfScope ps(st, 3);
+            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err};
+            if (p->T <= kSortTmaxSmall)
+                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)nbins), dim3(kCountBlock), 0,
+                                   st, ca);
+            else
+                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmax>), dim3((unsigned)nbins), dim3(kCountBlock), 0, st,
+                                   ca);
+            PB_LAUNCHED("row counts");
+            if (batch) {
+                PB_TRY(launch_scan<SegSumOp>(p->m, SegRowNnzSrc{L.rownnz, p->prob_row0, p->count},
+                                             SegRowPtrDst{{}, L.outs, p->prob_row0, p->count}, L.status, L.ticket, L.err,
+                                             st, "row pointer scan"));
+            } else {
+                PB_TRY(launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m}, L.status, L.ticket,
+                                          L.err, st, "row pointer scan"));
+            }
+        }
+        SortArgs sa{p->binrow0,
+                    p->binoff,
+                    L.keys,
+                    L.vals,
+                    p->cb,
+                    L.err,
+                    batch ? nullptr : C->rowptr,
+                    batch ? nullptr : C->colidx,
+                    batch ? nullptr : C->val,
+                    batch ? 0 : C->capacity,
+                    batch ? L.outs : nullptr,
+                    batch ? p->prob_row0 : nullptr,
+                    p->count};
+        ProfScope ps(st, 2);
+        if (p->T <= kSortTmaxSmall) {
+            if (f64)
+                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins),
+                                   dim3(kSortBlockSmall), 0, st, sa);
+            else
+                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins),
+                                   dim3(kSortBlockSmall), 0, st, sa);
+        } else {
+            if (f64)
+                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins),
+                                   dim3(kSortBlock), 0, st, sa);
+            else
+                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins),
+                                   dim3(kSortBlock), 0, st, sa);
+        }
+        PB_LAUNCHED("sort+compress");
     }
+    return PB_OK;
+}
+
+// ---- batch helpers --------------------------------------------------------
+pb_status check_batch(int32_t count, const pb_csx *A, const pb_csx *B) {
+    if (count < 1) return fail(PB_ERR_ARG, "count must be >= 1");
+    if (!A || !B) return fail(PB_ERR_ARG, "A/B arrays are NULL");
+    for (int32_t i = 0; i < count; ++i) {
+        char na[32], nb[32];
+        snprintf(na, sizeof na, "A[%d]", i);
+        snprintf(nb, sizeof nb, "B[%d]", i);
+        PB_TRY(check_csx(&A[i], na));
+        PB_TRY(check_csx(&B[i], nb));
+        if (A[i].ncols != B[i].nrows)
+            return fail(PB_ERR_SHAPE, "problem %d: A.ncols (%lld) != B.nrows (%lld)", i, (long long)A[i].ncols,
+                        (long long)B[i].nrows);
+    }
+    return PB_OK;
+}
+
+// Block-diagonal shapes and bases of a batch.
+void batch_shapes(int32_t count, const pb_csx *A, const pb_csx *B, std::vector<ProbDesc> &d, int64_t &m, int64_t &k,
+                  int64_t &n, int64_t &nnza, int64_t &nnzb) {
+    d.resize(count);
+    m = k = n = nnza = nnzb = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        ProbDesc &x = d[i];
+        x.aptr = A[i].ptr;
+        x.aidx = A[i].idx;
+        x.aval = A[i].val;
+        x.bptr = B[i].ptr;
+        x.bidx = B[i].idx;
+        x.bval = B[i].val;
+        x.m = A[i].nrows;
+        x.k = A[i].ncols;
+        x.n = B[i].ncols;
+        x.nnza = A[i].nnz;
+        x.nnzb = B[i].nnz;
+        x.mbase = m;
+        x.kbase = k;
+        x.abase = nnza;
+        x.bbase = nnzb;
+        m += x.m;
+        k += x.k;
+        nnza += x.nnza;
+        nnzb += x.nnzb;
+        n = x.n > n ? x.n : n;
+    }
+}
+
+pb_status ensure_pinned(pb_plan *p, size_t bytes) {
+    if (p->pinned_bytes >= bytes) return PB_OK;
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    p->pinned = nullptr;
+    p->pinned_bytes = 0;
+    PB_HIP(hipHostMalloc(&p->pinned, bytes, hipHostMallocDefault));
+    p->pinned_bytes = bytes;
+    return PB_OK;
+}
+
+// pinned staging layout: [ProbDesc x count][first rows x count][OutDesc x count]
+size_t staging_bytes(int32_t count) { return (sizeof(ProbDesc) + sizeof(int64_t) + sizeof(OutDesc)) * (size_t)count; }
+ProbDesc *staged_desc(pb_plan *p) { return (ProbDesc *)p->pinned; }
+int64_t *staged_row0(pb_plan *p) { return (int64_t *)((char *)p->pinned + sizeof(ProbDesc) * p->count); }
+OutDesc *staged_outs(pb_plan *p) {
+    return (OutDesc *)((char *)p->pinned + (sizeof(ProbDesc) + sizeof(int64_t)) * p->count);
+}
+
+pb_status launch_pack(pb_plan *p, int what, hipStream_t st) {
+    int64_t maxlen = 1;
+    for (const ProbDesc &d : p->hdesc) {
+        const int64_t l = std::max(d.k + 1, std::max(d.nnza, d.nnzb));
+        maxlen = l > maxlen ? l : maxlen;
+    }
+    int64_t gx = ceil_div(maxlen, 256 * 8);
+    gx = gx < 1 ? 1 : (gx > 256 ? 256 : gx);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)gx, (unsigned)p->count), dim3(256), 0, st, p->pdesc, p->count, what,
+                       p->acp, p->ari, p->av, p->brp, p->bci, p->bv);
+    PB_LAUNCHED("pack");
     return PB_OK;
 }
 
@@ -291,28 +519,29 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
                           size_t *sym_ws_bytes, void *hip_stream, pb_plan **plan, int64_t *flop,
                           size_t *workspace_bytes) {
     g_last_error.clear();
-    pb_status s;
-    if ((s = check_csx(A, "A", true)) != PB_OK) return s;
-    if ((s = check_csx(B, "B", false)) != PB_OK) return s;
-    if (A->ncols != B->nrows) return fail(PB_ERR_SHAPE, "A.ncols (%lld) != B.nrows (%lld)", (long long)A->ncols, (long long)B->nrows);
+    PB_TRY(check_csx(A, "A"));
+    PB_TRY(check_csx(B, "B"));
+    if (A->ncols != B->nrows)
+        return fail(PB_ERR_SHAPE, "A.ncols (%lld) != B.nrows (%lld)", (long long)A->ncols, (long long)B->nrows);
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
     int T, chunk;
-    if ((s = resolve_tune(tune, &T, &chunk)) != PB_OK) return s;
+    PB_TRY(resolve_tune(tune, &T, &chunk));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
-    const size_t need = sym_layout(nullptr, m, k, A->nnz).total;
+    const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1).total;
     if (!sym_ws) {
         *sym_ws_bytes = need;
         return PB_OK;
     }
-    if (*sym_ws_bytes < need) return fail(PB_ERR_WORKSPACE, "symbolic workspace has %zu bytes, needs %zu", *sym_ws_bytes, need);
+    if (*sym_ws_bytes < need)
+        return fail(PB_ERR_WORKSPACE, "symbolic workspace has %zu bytes, needs %zu", *sym_ws_bytes, need);
     if (!plan || !flop || !workspace_bytes) return fail(PB_ERR_ARG, "plan/flop/workspace_bytes output is NULL");
     if (B->nnz >= (int64_t)1 << 32) return fail(PB_ERR_RANGE, "nnz(B) must be below 2^32 (32-bit in-row run offsets)");
     const int cb = col_bits(n);
     if (cb > 31) return fail(PB_ERR_RANGE, "n too large for packed keys");
 
     hipStream_t st = (hipStream_t)hip_stream;
-    SymLayout L = sym_layout(sym_ws, m, k, A->nnz);
+    SymLayout L = sym_layout(sym_ws, m, k, A->nnz, B->nnz, 1);
     pb_plan *p = new pb_plan();
     p->m = m;
     p->k = k;
@@ -330,60 +559,17 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->runpos = L.runpos;
     p->binrow0 = L.binrow0;
     p->binoff = L.binoff;
-
-    pb_status rs = PB_OK;
-    {
+    pb_status rs = fill_zero(sym_ws, L.zero_bytes, st);
+    if (rs == PB_OK) {
         ProfScope ps(st, 0);
-        do {
-            if ((rs = fill_zero(sym_ws, L.zero_bytes, st)) != PB_OK) break;
-            if (k > 0) {
-                if ((rs = launch_scan<SumOp>(k, ColFlopSrc{A->ptr, B->ptr}, ColFlopDst{{}, L.F, k, L.info}, L.stF,
-                                             &L.tickets[0], &L.info->err, st, "flop scan")) != PB_OK)
-                    break;
-                const int64_t grid = ceil_div(k, 256);
-                hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)grid), dim3(256), 0, st, k, A->ptr, A->idx, B->ptr, L.R, L.runpos);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess) { rs = fail(PB_ERR_HIP, "launch rowflop: %s", hipGetErrorString(e)); break; }
-            } else {
-                if ((rs = fill_zero(L.F, sizeof(int64_t), st)) != PB_OK) break;
-            }
-            if (m > 0) {
-                if ((rs = launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(T / 2), L.info}, L.stR,
-                                             &L.tickets[1], &L.info->err, st, "row scan")) != PB_OK)
-                    break;
-                const int rowbits = 32 - cb;
-                if ((rs = launch_scan<BinOp>(m, BinSrc{L.R, L.info, (uint64_t)T, rowbits, nullptr, 0},
-                                             BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)T, L.info},
-                                             L.stB, &L.tickets[2], &L.info->err, st, "bin scan")) != PB_OK)
-                    break;
-            }
-        } while (0);
+        rs = run_symbolic(p, L, A->ptr, A->idx, B->ptr, st);
     }
+    if (rs == PB_OK) rs = finish_symbolic(p, st);
     if (rs != PB_OK) {
         delete p;
         return rs;
     }
-    hipError_t e = hipMemcpyAsync(&p->h, L.info, sizeof(SymInfo), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        delete p;
-        return fail(PB_ERR_HIP, "symbolic readback: %s", hipGetErrorString(e));
-    }
-    if (p->h.err) {
-        uint32_t er = p->h.err;
-        delete p;
-        return fail(PB_ERR_INTERNAL, "symbolic device error 0x%x", er);
-    }
-    if (m == 0) p->h.nbins = 0;
-    if (p->h.noversize) {
-        const unsigned long long nov = (unsigned long long)p->h.noversize;
-        const long long mr = (long long)p->h.maxrow;
-        delete p;
-        return fail(PB_ERR_UNSUPPORTED, "%llu rows expand to more than %d tuples (largest %lld); "
-                    "bins larger than the LDS tile are not supported", nov, T, mr);
-    }
-    p->nchunks = ceil_div((int64_t)p->h.flop, chunk);
-    p->ws_bytes = num_layout(nullptr, p).total;
+    p->prob_flop.assign(1, (int64_t)p->h.flop);
     *plan = p;
     *flop = (int64_t)p->h.flop;
     *workspace_bytes = p->ws_bytes;
@@ -394,9 +580,9 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
                          pb_csr_out *C, int64_t *nnzC, void *hip_stream) {
     g_last_error.clear();
     if (!p) return fail(PB_ERR_ARG, "plan is NULL");
-    pb_status s;
-    if ((s = check_csx(A, "A", true)) != PB_OK) return s;
-    if ((s = check_csx(B, "B", false)) != PB_OK) return s;
+    if (p->count != 1) return fail(PB_ERR_ARG, "the plan is a batch plan: use spgemm_batched");
+    PB_TRY(check_csx(A, "A"));
+    PB_TRY(check_csx(B, "B"));
     if (A->nrows != p->m || A->ncols != p->k || B->ncols != p->n || A->nnz != p->nnzA || B->nnz != p->nnzB)
         return fail(PB_ERR_SHAPE, "A/B differ from the matrices given to the symbolic step");
     if (!C || !C->rowptr) return fail(PB_ERR_ARG, "C or C->rowptr is NULL");
@@ -406,62 +592,10 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
         return fail(PB_ERR_WORKSPACE, "numeric workspace has %zu bytes, needs %zu", workspace_bytes, p->ws_bytes);
 
     hipStream_t st = (hipStream_t)hip_stream;
-    const int64_t flop = (int64_t)p->h.flop;
-    const int64_t nbins = (int64_t)p->h.nbins;
     NumLayout L = num_layout(workspace, p);
-    if ((s = fill_zero(workspace, L.zero_bytes, st)) != PB_OK) return s;
-    if (p->m == 0) {
-        if ((s = fill_zero(C->rowptr, sizeof(int64_t), st)) != PB_OK) return s;
-    }
-    if (flop > 0) {
-        const int64_t nthreads = p->nchunks + 1;
-        hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(nthreads, 256)), dim3(256), 0, st, p->nchunks,
-                           (int64_t)p->chunk, p->k, p->F, L.kstart);
-        PB_LAUNCHED("chunk start");
-        ExpandArgs ea{flop, p->k, p->F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val,
-                      p->runpos, p->rowtab, L.keys, L.vals, p->cb, L.err};
-        ProfScope ps(st, 1);
-        if (p->chunk == 4096) {
-            if (p->prec == PB_F64)
-                hipLaunchKernelGGL((k_expand<kExpBlock, 16, kExpWin, double>), dim3((unsigned)p->nchunks), dim3(kExpBlock), 0, st, ea);
-            else
-                hipLaunchKernelGGL((k_expand<kExpBlock, 16, kExpWin, float>), dim3((unsigned)p->nchunks), dim3(kExpBlock), 0, st, ea);
-        } else {
-            if (p->prec == PB_F64)
-                hipLaunchKernelGGL((k_expand<kExpBlock, 8, kExpWin, double>), dim3((unsigned)p->nchunks), dim3(kExpBlock), 0, st, ea);
-            else
-                hipLaunchKernelGGL((k_expand<kExpBlock, 8, kExpWin, float>), dim3((unsigned)p->nchunks), dim3(kExpBlock), 0, st, ea);
-        }
-        PB_LAUNCHED("expand");
-    }
-    if (nbins > 0) {
-        {
-            ProfScope ps(st, 3);
-            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err};
-            if (p->T <= kSortTmaxSmall)
-                hipLaunchKernelGGL((k_row_nnz<512, kSortTmaxSmall>), dim3((unsigned)nbins), dim3(512), 0, st, ca);
-            else
-                hipLaunchKernelGGL((k_row_nnz<512, kSortTmax>), dim3((unsigned)nbins), dim3(512), 0, st, ca);
-            PB_LAUNCHED("row counts");
-            if ((s = launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m}, L.status, L.ticket,
-                                        L.err, st, "row pointer scan")) != PB_OK)
-                return s;
-        }
-        SortArgs sa{p->binrow0, p->binoff, L.keys, L.vals, p->cb, L.err, C->rowptr, C->colidx, C->val, C->capacity};
-        ProfScope ps(st, 2);
-        if (p->T <= kSortTmaxSmall) {
-            if (p->prec == PB_F64)
-                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins), dim3(kSortBlockSmall), 0, st, sa);
-            else
-                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins), dim3(kSortBlockSmall), 0, st, sa);
-        } else {
-            if (p->prec == PB_F64)
-                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins), dim3(kSortBlock), 0, st, sa);
-            else
-                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins), dim3(kSortBlock), 0, st, sa);
-        }
-        PB_LAUNCHED("sort+compress");
-    }
+    PB_TRY(fill_zero(workspace, L.zero_bytes, st));
+    if (p->m == 0) PB_TRY(fill_zero(C->rowptr, sizeof(int64_t), st));
+    PB_TRY(run_numeric(p, L, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, C, st));
     if (nnzC) {
         int64_t total = 0;
         uint32_t err = 0;
@@ -471,7 +605,179 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
         *nnzC = total;
         if (err & ~(uint32_t)kErrCapacity) return fail(PB_ERR_INTERNAL, "numeric device error 0x%x", err);
         if ((err & kErrCapacity) || total > C->capacity)
-            return fail(PB_ERR_CAPACITY, "C needs %lld entries, capacity %lld", (long long)total, (long long)C->capacity);
+            return fail(PB_ERR_CAPACITY, "C needs %lld entries, capacity %lld", (long long)total,
+                        (long long)C->capacity);
+    }
+    return PB_OK;
+}
+
+pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *B, pb_precision prec,
+                                  const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes, void *hip_stream,
+                                  pb_plan **plan, int64_t *flop, size_t *workspace_bytes) {
+    g_last_error.clear();
+    PB_TRY(check_batch(count, A, B));
+    if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
+    if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
+    int T, chunk;
+    PB_TRY(resolve_tune(tune, &T, &chunk));
+    std::vector<ProbDesc> hd;
+    int64_t m, k, n, nnza, nnzb;
+    batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);
+    if (m > kMaxDim || k > kMaxDim) return fail(PB_ERR_RANGE, "batch rows / inner dimension exceed 2^31-1 in total");
+    // the device tables always hold at least two problems (a batch of one
+    // gets an empty second problem) so that the batch code paths apply
+    const int32_t cnt = count > 1 ? count : 2;
+    const size_t need = sym_layout(nullptr, m, k, nnza, nnzb, cnt).total;
+    if (!sym_ws) {
+        *sym_ws_bytes = need;
+        return PB_OK;
+    }
+    if (*sym_ws_bytes < need)
+        return fail(PB_ERR_WORKSPACE, "symbolic workspace has %zu bytes, needs %zu", *sym_ws_bytes, need);
+    if (!plan || !flop || !workspace_bytes) return fail(PB_ERR_ARG, "plan/flop/workspace_bytes output is NULL");
+    if (nnzb >= (int64_t)1 << 32) return fail(PB_ERR_RANGE, "nnz(B) must be below 2^32 (32-bit in-row run offsets)");
+    const int cb = col_bits(n);
+    if (cb > 31) return fail(PB_ERR_RANGE, "n too large for packed keys");
+    if (count == 1) {
+        ProbDesc e{};
+        e.mbase = hd[0].m;
+        e.kbase = hd[0].k;
+        e.abase = hd[0].nnza;
+        e.bbase = hd[0].nnzb;
+        hd.push_back(e);
+    }
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    SymLayout L = sym_layout(sym_ws, m, k, nnza, nnzb, cnt);
+    pb_plan *p = new pb_plan();
+    p->m = m;
+    p->k = k;
+    p->n = n;
+    p->nnzA = nnza;
+    p->nnzB = nnzb;
+    p->count = cnt;
+    p->user_count = count;
+    p->prec = prec;
+    p->T = T;
+    p->chunk = chunk;
+    p->cb = cb;
+    p->info = L.info;
+    p->F = L.F;
+    p->R = L.R;
+    p->rowtab = L.rowtab;
+    p->runpos = L.runpos;
+    p->binrow0 = L.binrow0;
+    p->binoff = L.binoff;
+    p->pdesc = L.pdesc;
+    p->prob_row0 = L.prob_row0;
+    p->acp = L.acp;
+    p->brp = L.brp;
+    p->ari = L.ari;
+    p->bci = L.bci;
+    p->av = L.av;
+    p->bv = L.bv;
+    p->hdesc = hd;
+    pb_status rs = ensure_pinned(p, staging_bytes(cnt));
+    if (rs == PB_OK) {
+        std::memcpy(staged_desc(p), hd.data(), sizeof(ProbDesc) * cnt);
+        int64_t *pr = staged_row0(p);
+        for (int32_t i = 0; i < cnt; ++i) pr[i] = hd[i].mbase;
+        if (hipMemcpyAsync(L.pdesc, staged_desc(p), sizeof(ProbDesc) * cnt, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(L.prob_row0, pr, sizeof(int64_t) * cnt, hipMemcpyHostToDevice, st) != hipSuccess)
+            rs = fail(PB_ERR_HIP, "descriptor upload failed");
+    }
+    if (rs == PB_OK) rs = fill_zero(sym_ws, L.zero_bytes, st);
+    if (rs == PB_OK) {
+        ProfScope ps(st, 0);
+        rs = launch_pack(p, 1, st);
+        if (rs == PB_OK) rs = run_symbolic(p, L, L.acp, L.ari, L.brp, st);
+    }
+    if (rs == PB_OK) rs = finish_symbolic(p, st);
+    // per-problem flop: the flop scan at the problems' first columns
+    std::vector<int64_t> Fb(cnt + 1, 0);
+    for (int32_t i = 0; rs == PB_OK && i <= cnt; ++i) {
+        const int64_t col = i < cnt ? hd[i].kbase : k;
+        if (hipMemcpyAsync(&Fb[i], L.F + col, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+            rs = fail(PB_ERR_HIP, "flop readback failed");
+    }
+    if (rs == PB_OK && hipStreamSynchronize(st) != hipSuccess) rs = fail(PB_ERR_HIP, "flop readback failed");
+    if (rs != PB_OK) {
+        delete p;
+        return rs;
+    }
+    p->prob_flop.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        p->prob_flop[i] = Fb[i + 1] - Fb[i];
+        flop[i] = p->prob_flop[i];
+    }
+    *plan = p;
+    *workspace_bytes = p->ws_bytes;
+    return PB_OK;
+}
+
+pb_status spgemm_batched(pb_plan *p, int32_t count, const pb_csx *A, const pb_csx *B, void *workspace,
+                         size_t workspace_bytes, pb_csr_out *C, int64_t *nnzC, void *hip_stream) {
+    g_last_error.clear();
+    if (!p) return fail(PB_ERR_ARG, "plan is NULL");
+    if (p->count < 2) return fail(PB_ERR_ARG, "the plan is a single-product plan: use spgemm_numeric");
+    if (count != p->user_count) return fail(PB_ERR_SHAPE, "count differs from the symbolic step");
+    PB_TRY(check_batch(count, A, B));
+    if (!C) return fail(PB_ERR_ARG, "C is NULL");
+    for (int32_t i = 0; i < count; ++i) {
+        const ProbDesc &d = p->hdesc[i];
+        if (A[i].nrows != d.m || A[i].ncols != d.k || B[i].ncols != d.n || A[i].nnz != d.nnza || B[i].nnz != d.nnzb)
+            return fail(PB_ERR_SHAPE, "problem %d differs from the symbolic step", i);
+        if (!C[i].rowptr) return fail(PB_ERR_ARG, "C[%d].rowptr is NULL", i);
+        if (C[i].capacity < 0) return fail(PB_ERR_SHAPE, "C[%d] has negative capacity", i);
+        if (C[i].capacity > 0 && (!C[i].colidx || !C[i].val)) return fail(PB_ERR_ARG, "C[%d].colidx/val is NULL", i);
+    }
+    if (p->ws_bytes > 0 && (!workspace || workspace_bytes < p->ws_bytes))
+        return fail(PB_ERR_WORKSPACE, "numeric workspace has %zu bytes, needs %zu", workspace_bytes, p->ws_bytes);
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    NumLayout L = num_layout(workspace, p);
+    const int32_t cnt = p->count;
+    // input descriptors (the arrays may have moved since the symbolic step)
+    // and output descriptors, through the pinned staging area
+    ProbDesc *sd = staged_desc(p);
+    OutDesc *so = staged_outs(p);
+    for (int32_t i = 0; i < cnt; ++i) {
+        sd[i] = p->hdesc[i];
+        if (i < count) {
+            sd[i].aptr = A[i].ptr;
+            sd[i].aidx = A[i].idx;
+            sd[i].aval = A[i].val;
+            sd[i].bptr = B[i].ptr;
+            sd[i].bidx = B[i].idx;
+            sd[i].bval = B[i].val;
+            so[i] = OutDesc{C[i].rowptr, C[i].colidx, C[i].val, C[i].capacity, sd[i].mbase, sd[i].m};
+        } else {
+            so[i] = OutDesc{nullptr, nullptr, nullptr, 0, sd[i].mbase, 0};
+        }
+    }
+    PB_HIP(hipMemcpyAsync(p->pdesc, sd, sizeof(ProbDesc) * cnt, hipMemcpyHostToDevice, st));
+    PB_HIP(hipMemcpyAsync(L.outs, so, sizeof(OutDesc) * cnt, hipMemcpyHostToDevice, st));
+    PB_TRY(fill_zero(workspace, L.zero_bytes, st));
+    PB_TRY(launch_pack(p, 2, st));
+    for (int32_t i = 0; i < count; ++i)
+        if (p->hdesc[i].m == 0) PB_TRY(fill_zero(C[i].rowptr, sizeof(int64_t), st));
+    PB_TRY(run_numeric(p, L, p->acp, p->ari, p->av, p->brp, p->bci, p->bv, nullptr, st));
+    if (nnzC) {
+        std::vector<int64_t> tot(count, 0);
+        uint32_t err = 0;
+        for (int32_t i = 0; i < count; ++i)
+            PB_HIP(hipMemcpyAsync(&tot[i], C[i].rowptr + p->hdesc[i].m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        PB_HIP(hipMemcpyAsync(&err, L.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        PB_HIP(hipStreamSynchronize(st));
+        if (err & ~(uint32_t)kErrCapacity) return fail(PB_ERR_INTERNAL, "numeric device error 0x%x", err);
+        pb_status rs = PB_OK;
+        for (int32_t i = 0; i < count; ++i) {
+            nnzC[i] = tot[i];
+            if (tot[i] > C[i].capacity && rs == PB_OK)
+                rs = fail(PB_ERR_CAPACITY, "C[%d] needs %lld entries, capacity %lld", i, (long long)tot[i],
+                          (long long)C[i].capacity);
+        }
+        return rs;
     }
     return PB_OK;
 }
@@ -484,13 +790,13 @@ pb_status spgemm_plan_info(const pb_plan *p, pb_plan_info *info) {
     info->n = p->n;
     info->flop = (int64_t)p->h.flop;
     info->nbins = (int64_t)p->h.nbins;
-    info->max_bin_tuples = -1;
+    info->max_bin_tuples = p->T;
     info->max_row_flop = (int64_t)p->h.maxrow;
     info->tile_tuples = p->T;
     info->expand_chunk = p->chunk;
     info->col_bits = p->cb;
     info->precision = (int32_t)p->prec;
-    info->count = 1;
+    info->count = p->user_count;
     return PB_OK;
 }
 
@@ -531,7 +837,8 @@ pb_status spgemm_copy(void *dst, const void *src, size_t bytes, void *hip_stream
     if (n == 0) return PB_OK;
     const int64_t grid = ceil_div(n, 256);
     if (grid > 0x7fffffffll) return fail(PB_ERR_RANGE, "copy too large");
-    hipLaunchKernelGGL(k_copy16, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)hip_stream, (uint4 *)dst, (const uint4 *)src, n);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)hip_stream, (uint4 *)dst,
+                       (const uint4 *)src, n);
     PB_LAUNCHED("copy");
     return PB_OK;
 }

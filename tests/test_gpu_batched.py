@@ -1,0 +1,135 @@
+"""GPU parity for batched products C_i = A_i * B_i (one block-diagonal
+launch set for the whole batch), including a HIP-graph capture."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Csx, batched_er_sizes, er_problem, random_sparse
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": 1e-12, "f32c": 1e-6}
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pb():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2002_11302_amd as pbm
+
+    pbm.load()
+    return pbm
+
+
+def _empty(m, k, fmt):
+    nmaj = k if fmt == "csc" else m
+    return Csx(m, k, np.zeros(nmaj + 1, np.int64), np.zeros(0, np.int32), np.zeros(0), fmt)
+
+
+def _uneven_batch(seed=5):
+    probs = []
+    rng = np.random.default_rng(seed)
+    for i in range(10):
+        n = int(rng.integers(50, 3000))
+        d = int(rng.integers(1, 9))
+        probs.append(er_problem(n, d, 100 + i, 200 + i, values="signed"))
+    probs.append((random_sparse(300, 200, 0.02, 7, "csc"), random_sparse(200, 250, 0.02, 8, "csr")))
+    probs.append((_empty(0, 40, "csc"), random_sparse(40, 30, 0.1, 9, "csr")))    # no rows
+    probs.append((_empty(25, 0, "csc"), _empty(0, 35, "csr")))                      # inner dimension 0
+    probs.append((random_sparse(64, 50, 0.0, 10, "csc"), random_sparse(50, 64, 0.1, 11, "csr")))  # empty A
+    return probs
+
+
+def _check(got: dict, ref: dict, precision: str):
+    assert np.array_equal(got["rowptr"], ref["rowptr"])
+    assert np.array_equal(got["colidx"], ref["colidx"])
+    err = np.abs(got["val"].astype(np.float64) - ref["val"])
+    assert np.all(err <= TOL[precision] * ref["absval"])
+
+
+def _ref(a, b):
+    if a.nrows == 0:
+        return dict(rowptr=np.zeros(1, np.int64), colidx=np.zeros(0, np.int32), val=np.zeros(0), absval=np.zeros(0))
+    return oracle.spgemm(a, b)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_uneven_batch(pb, precision):
+    _say(f"uneven batch of 14 {precision}")
+    probs = _uneven_batch()
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    outs = pb.spgemm_batch(pairs, precision=precision)
+    for (a, b), c in zip(probs, outs):
+        _check(c.to_host(), _ref(a, b), precision)
+
+
+def test_batch_of_one_and_single_path_agree(pb):
+    _say("batch of one vs single product")
+    a, b = er_problem(5000, 6, 31, 32, values="signed")
+    A, B = pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)
+    (cb,) = pb.spgemm_batch([(A, B)])
+    cs = pb.spgemm(A, B)
+    gb, gs = cb.to_host(), cs.to_host()
+    assert np.array_equal(gb["rowptr"], gs["rowptr"]) and np.array_equal(gb["colidx"], gs["colidx"])
+    _check(gb, oracle.spgemm(a, b), "f64")
+
+
+def test_batch_sizes_like_workload(pb):
+    """The batched workload's size law (log-uniform n, d in 2..32), scaled
+    down to n <= 2^12 so the oracle stays fast."""
+    _say("log-uniform batch of 48, n <= 2^12")
+    n, d = batched_er_sizes(48, seed=4, lo_log2=6, hi_log2=12)
+    probs = [er_problem(int(n[i]), int(min(d[i], n[i] // 4)), 1000 + i, 2000 + i, values="signed") for i in range(48)]
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    for prec in ("f64", "f32c"):
+        outs = pb.spgemm_batch(pairs, precision=prec, tune={"tile_tuples": 4096})
+        for (a, b), c in zip(probs, outs):
+            _check(c.to_host(), oracle.spgemm(a, b), prec)
+
+
+def test_graph_capture_replays(pb):
+    """The numeric step enqueues work only (no sync): capture it in a HIP
+    graph and replay it several times, with eager work and synchronisations
+    between replays; every replay must equal the eager result."""
+    import torch
+
+    _say("hipGraph capture of the batched numeric step")
+    probs = _uneven_batch(seed=9)[:8]
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    nsym = pb.spgemm_batched_symbolic(pairs)
+    plan = pb.spgemm_batched_symbolic(pairs, sym_ws=torch.empty(nsym, dtype=torch.uint8, device="cuda"))
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+    outs = [(torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda"),
+             torch.empty(max(f, 1), dtype=torch.int32, device="cuda"),
+             torch.empty(max(f, 1), dtype=torch.float64, device="cuda")) for (a, _), f in zip(pairs, plan.flops)]
+    nnz = pb.spgemm_batched(plan, pairs, ws, outs, sync=True)
+    eager = [(rp.clone(), ci[:z].clone(), cv[:z].clone()) for (rp, ci, cv), z in zip(outs, nnz)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=side)  # warm-up on the side stream
+        side.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for rp, ci, cv in outs:  # scribble over the outputs between replays
+            rp.fill_(-1)
+            ci.fill_(-1)
+            cv.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (rp, ci, cv), (erp, eci, ecv), z in zip(outs, eager, nnz):
+            assert torch.equal(rp, erp), f"replay {rep}: row pointers"
+            assert torch.equal(ci[:z], eci), f"replay {rep}: columns"
+            assert torch.allclose(cv[:z], ecv, rtol=1e-12, atol=0), f"replay {rep}: values"
+    plan.close()

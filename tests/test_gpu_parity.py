@@ -85,7 +85,7 @@ def test_er_signed_several_tiles(pb, precision):
 
 
 @pytest.mark.parametrize("tile", [256, 1000, 4096])
-@pytest.mark.parametrize("chunk", [2048, 4096])
+@pytest.mark.parametrize("chunk", [512, 2048])
 def test_tiles_and_chunks(pb, tile, chunk):
     _say(f"ER n=20011 d=6 tile={tile} chunk={chunk}")
     a, b = er_problem(20011, 6, 7, 8)
