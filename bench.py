@@ -143,6 +143,169 @@ def cpu_baseline(a, b):
                       f"{dt:.2f} s wall on {threads} host threads"}
 
 
+def fp32c_error(pb, torch, a, b, A, B, nrows_sample=2000):
+    """Max |C_f32c - C_oracle| / N over sampled rows (N = |A||B|)."""
+    import oracle
+
+    c = pb.spgemm(A, B, precision="f32c")
+    rng = np.random.default_rng(7)
+    rows = np.unique(rng.integers(0, a.nrows, nrows_sample))
+    ref = oracle.spgemm_rows(a, b, rows)
+    rp = c.rowptr.cpu().numpy()
+    cv = c.val.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for s_, r in enumerate(rows):
+        g = cv[rp[r]:rp[r + 1]]
+        want = ref["val"][ref["ptr"][s_]:ref["ptr"][s_ + 1]]
+        nrm = ref["absval"][ref["ptr"][s_]:ref["ptr"][s_ + 1]]
+        if g.size:
+            worst = max(worst, float(np.max(np.abs(g - want) / nrm)))
+    return worst
+
+
+def bench_batched(pb, torch, steps, warmup):
+    """Batched ER workload: 512 products, n_i log-uniform in [2^10, 2^17],
+    d_i in {2..32}, values U[-1,1).  Numeric step captured once in a HIP graph
+    and replayed; compared with the plain FP64 path run product by product."""
+    from paper_2002_11302_amd import autotune
+    from workloads import batched_er_problems, batched_er_sizes
+
+    t = time.time()
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in batched_er_problems(512)]
+    nvec, dvec = batched_er_sizes(512)
+    torch.cuda.synchronize()
+    log(f"batched: generated and uploaded 512 problems in {time.time() - t:.1f}s")
+    res = {"workload": "512 ER products, n_i log-uniform in [2^10,2^17], d_i in {2..32}, values U[-1,1)"}
+    for prec in ("f64", "f32c"):
+        vdt = torch.float64 if prec == "f64" else torch.float32
+        cache = {}
+
+        def prepared(tune):
+            key = (tune["tile_tuples"], tune["expand_chunk"])
+            if key not in cache:
+                cache.clear()
+                nsym = pb.spgemm_batched_symbolic(pairs, prec, tune)
+                sym = torch.empty(nsym, dtype=torch.uint8, device="cuda")
+                plan = pb.spgemm_batched_symbolic(pairs, prec, tune, sym_ws=sym)
+                ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+                cache[key] = (sym, plan, ws)
+            return cache[key]
+
+        flops = None
+        outs = None
+
+        def run(tune):
+            nonlocal flops, outs
+            sym, plan, ws = prepared(tune)
+            if outs is None:
+                flops = plan.flops
+                outs = [(torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda"),
+                         torch.empty(max(f, 1), dtype=torch.int32, device="cuda"),
+                         torch.empty(max(f, 1), dtype=vdt, device="cuda")) for (a, _), f in zip(pairs, plan.flops)]
+            pb.spgemm_batched(plan, pairs, ws, outs, sync=True)
+
+        key = autotune.size_class(512, (dvec * dvec * nvec).tolist(), int(nvec.max()), prec)
+        best = autotune.tune(run, key, log=log)
+        tune = {"tile_tuples": best["tile_tuples"], "expand_chunk": best["expand_chunk"]}
+        sym, plan, ws = prepared(tune)
+        run(tune)
+        tot_flop = int(sum(plan.flops))
+        # whole path (symbolic + numeric) per step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p2 = pb.spgemm_batched_symbolic(pairs, prec, tune, sym_ws=sym)
+            pb.spgemm_batched(p2, pairs, ws, outs, sync=False)
+            p2.close()
+        torch.cuda.synchronize()
+        whole = (time.perf_counter() - t0) / steps
+        # numeric step as one graph
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=side)
+            side.synchronize()
+            with torch.cuda.graph(g, stream=side):
+                pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=side)
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / steps
+        nnz = sum(int(o[0][-1].item()) for o in outs)
+        res[prec] = {"tune": tune, "autotune_cached": best.get("cached"), "autotune_timings_ms": best.get("timings_ms"),
+                     "flop": tot_flop, "nnz_c": nnz,
+                     "whole_path_ms": round(whole * 1e3, 3), "whole_path_GFLOPS": round(2 * tot_flop / whole / 1e9, 2),
+                     "numeric_graph_ms": round(graph_ms, 3),
+                     "numeric_graph_GFLOPS": round(2 * tot_flop / (graph_ms * 1e-3) / 1e9, 2),
+                     "model_GB_without_C": round(sum(model_bytes(a.nrows, a.ncols, a.nnz, b.nnz, f, 0, prec)["total"]
+                                           for (a, b), f in zip(pairs, plan.flops)) / 1e9, 2)}
+        log(f"batched {prec}: {res[prec]['whole_path_GFLOPS']} GFLOPS whole path, "
+            f"{res[prec]['numeric_graph_GFLOPS']} GFLOPS numeric graph")
+        del g, outs, cache
+        outs = None
+        torch.cuda.empty_cache()
+    # the plain FP64 path, one product at a time
+    outs = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in pairs:
+        pb.spgemm(a, b)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    res["sequential_f64_ms"] = round(seq * 1e3, 2)
+    res["sequential_f64_GFLOPS"] = round(2 * res["f64"]["flop"] / seq / 1e9, 2)
+    res["speedup_batched_f64_vs_sequential_f64"] = round(seq / (res["f64"]["whole_path_ms"] * 1e-3), 2)
+    res["speedup_batched_f32c_vs_sequential_f64"] = round(seq / (res["f32c"]["whole_path_ms"] * 1e-3), 2)
+    return res
+
+
+def bench_amg(pb, torch, steps, warmup):
+    """AMG Galerkin chain on the 128^3 7-point Laplacian: T = A*P, Ac = R*T."""
+    from workloads import Csx, amg_problem
+
+    A, P = amg_problem(128)
+    Ad = pb.DeviceCsx.from_host(Csx(A.nrows, A.ncols, A.ptr, A.idx, A.val, "csc"))
+    Pd = pb.DeviceCsx.from_host(P)
+    Rd = Pd.transpose_view()
+    res = {"workload": "AMG R*(A*P), 7-point Laplacian 128^3, smoothed aggregation 2x2x2, omega=2/3"}
+    # multiplications of both products, from the plans of the first run
+    T0 = pb.spgemm(Ad, Pd)
+    f1 = pb.spgemm_symbolic(Ad, Pd, sym_ws=torch.empty(pb.spgemm_symbolic(Ad, Pd), dtype=torch.uint8, device="cuda"))
+    T0d = pb.DeviceCsx(T0.nrows, T0.ncols, T0.rowptr, T0.colidx, T0.val)
+    f2 = pb.spgemm_symbolic(Rd, T0d, sym_ws=torch.empty(pb.spgemm_symbolic(Rd, T0d), dtype=torch.uint8, device="cuda"))
+    flop_chain = f1.flop + f2.flop
+    res["flop"] = [f1.flop, f2.flop]
+    f1.close()
+    f2.close()
+    for prec in ("f64", "f32c"):
+        def chain():
+            T = pb.spgemm(Ad, Pd, precision=prec)
+            Td = pb.DeviceCsx(T.nrows, T.ncols, T.rowptr, T.colidx, T.val.to(torch.float64))
+            return T, pb.spgemm(Rd, Td, precision=prec)
+
+        for _ in range(warmup):
+            chain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            T, Ac = chain()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        flop = flop_chain
+        res[prec] = {"chain_ms": round(dt * 1e3, 3), "GFLOPS": round(2 * flop / dt / 1e9, 2),
+                     "nnz_T": T.nnz, "nnz_Ac": Ac.nnz}
+        log(f"amg {prec}: {dt * 1e3:.3f} ms per chain")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,7 +313,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["f64", "f32c"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time FP32c and the copy bandwidth")
+    ap.add_argument("--extras", action="store_true", help="also time FP32c (with its error) and the copy bandwidth")
+    ap.add_argument("--batched", action="store_true", help="also run the 512-product batched workload")
+    ap.add_argument("--amg", action="store_true", help="also run the AMG Galerkin chain")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding).",
@@ -209,6 +374,13 @@ def main():
             f"{other}_phases_ms": {k: round(ms / max(n, 1), 5) for k, (ms, n) in prof2.items()},
             "copy_GBps": round(copy_bandwidth(pb, torch), 1),
         }
+        out["extras"][f"{other}_speedup_vs_{args.precision}"] = round(sec / sec2, 3)
+        if other == "f32c":
+            out["extras"]["f32c_max_err_over_N_sampled_rows"] = fp32c_error(pb, torch, a, b, A, B)
+    if args.amg:
+        out.setdefault("extras", {})["amg"] = bench_amg(pb, torch, max(3, args.steps // 4), 1)
+    if args.batched:
+        out.setdefault("extras", {})["batched"] = bench_batched(pb, torch, max(2, args.steps // 10), 1)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
         out["cpu_baseline"] = cpu_baseline(a, b)
