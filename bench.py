@@ -306,6 +306,74 @@ def bench_amg(pb, torch, steps, warmup):
     return res
 
 
+def summarize_profiles(src: str, out_dir: str, command: str) -> None:
+    """Turn rocprofv3 CSV output (kernel trace stats and two counter runs,
+    FETCH_SIZE then WRITE_SIZE) into the text summaries under profiles/ and
+    the per-launch HBM traffic table bench.py reports.  The counters are
+    scaled by what they read for the 16-byte copy kernel of known size."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        files = glob.glob(os.path.join(src, pattern), recursive=True)
+        if not files:
+            raise FileNotFoundError(pattern)
+        with open(files[0]) as f:
+            return list(csv.DictReader(f))
+
+    def short(name):
+        for key in ("k_expand", "k_sort_compress", "k_row_nnz", "k_rowflop", "k_chained_scan", "k_chunk_start",
+                    "k_copy16", "k_fill_u32", "k_pack"):
+            if key in name:
+                prec = "f32c" if "float" in name else ("f64" if "double" in name else "")
+                return f"{key}<{prec}>" if prec else key
+        return name[:40]
+
+    stats = rows("kt/**/*kernel_stats.csv")
+    lines = [f"# rocprofv3 kernel-trace summary: ER n=2^20 d=16 A*B (bench.py workload)",
+             f"# command: {command}",
+             f"# {'kernel':58s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in stats:
+        lines.append(f"  {r['Name'][:58]:58s} {r['Calls']:>6s} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "kernels_er2e20_d16.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def per_kernel(kind):
+        acc = {}
+        for r in rows(f"{kind}/**/*counter_collection.csv"):
+            if r.get("Counter_Name") != kind.upper() + "_SIZE":
+                continue
+            k = short(r["Kernel_Name"])
+            acc.setdefault(k, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = per_kernel("fetch"), per_kernel("write")
+    copy_bytes = 4 << 30
+    f_scale = copy_bytes / (fetch["k_copy16"] * 1024.0)
+    w_scale = copy_bytes / (write["k_copy16"] * 1024.0)
+    sha = kernel_source_sha()
+    traffic = {"_calibration": {"copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
+                                "kernel_source_sha256": sha}}
+    lines = ["# HBM traffic per launch from rocprofv3 counters (FETCH_SIZE and WRITE_SIZE, KiB per dispatch),",
+             f"# scaled by the copy kernel: fetch x{f_scale:.3f}, write x{w_scale:.3f} (4 GiB copy reads and writes 4 GiB)",
+             "# commands: rocprofv3 --pmc FETCH_SIZE ... and rocprofv3 --pmc WRITE_SIZE ... -- " + command.split(" -- ", 1)[-1],
+             f"# {'kernel':28s} {'fetch_KiB':>14s} {'write_KiB':>14s} {'fetch_GB':>10s} {'write_GB':>10s}"]
+    for k in sorted(set(fetch) | set(write)):
+        fb = fetch.get(k, 0.0) * 1024 * f_scale
+        wb = write.get(k, 0.0) * 1024 * w_scale
+        lines.append(f"  {k:28s} {fetch.get(k, 0.0):14.1f} {write.get(k, 0.0):14.1f} {fb / 1e9:10.3f} {wb / 1e9:10.3f}")
+        if k.startswith(("k_expand", "k_sort_compress", "k_row_nnz")):
+            traffic[k] = {"bytes_per_launch": int(fb + wb), "fetch_bytes": int(fb), "write_bytes": int(wb),
+                          "kernel_source_sha256": sha}
+    with open(os.path.join(out_dir, "hbm_traffic_er2e20_d16.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(out_dir, "traffic.json"), "w") as f:
+        json.dump(traffic, f, indent=1, sort_keys=True)
+        f.write("\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,7 +384,12 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also time FP32c (with its error) and the copy bandwidth")
     ap.add_argument("--batched", action="store_true", help="also run the 512-product batched workload")
     ap.add_argument("--amg", action="store_true", help="also run the AMG Galerkin chain")
+    ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
+    ap.add_argument("--profile-command", default="", help="the profiled command, recorded in the summaries")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding).",
               file=sys.stderr)
