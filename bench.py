@@ -306,7 +306,7 @@ def bench_amg(pb, torch, steps, warmup):
     return res
 
 
-def summarize_profiles(src: str, out_dir: str, command: str) -> None:
+def summarize_profiles(src: str, out_dir: str, command: str, pmc_command: str) -> None:
     """Turn rocprofv3 CSV output (kernel trace stats and two counter runs,
     FETCH_SIZE then WRITE_SIZE) into the text summaries under profiles/ and
     the per-launch HBM traffic table bench.py reports.  The counters are
@@ -358,7 +358,8 @@ def summarize_profiles(src: str, out_dir: str, command: str) -> None:
                                 "kernel_source_sha256": sha}}
     lines = ["# HBM traffic per launch from rocprofv3 counters (FETCH_SIZE and WRITE_SIZE, KiB per dispatch),",
              f"# scaled by the copy kernel: fetch x{f_scale:.3f}, write x{w_scale:.3f} (4 GiB copy reads and writes 4 GiB)",
-             "# commands: rocprofv3 --pmc FETCH_SIZE ... and rocprofv3 --pmc WRITE_SIZE ... -- " + command.split(" -- ", 1)[-1],
+             "# commands: " + pmc_command.replace("{COUNTER}", "FETCH_SIZE").replace("{KIND}", "fetch"),
+             "#      and: " + pmc_command.replace("{COUNTER}", "WRITE_SIZE").replace("{KIND}", "write"),
              f"# {'kernel':28s} {'fetch_KiB':>14s} {'write_KiB':>14s} {'fetch_GB':>10s} {'write_GB':>10s}"]
     for k in sorted(set(fetch) | set(write)):
         fb = fetch.get(k, 0.0) * 1024 * f_scale
@@ -385,13 +386,17 @@ def main():
     ap.add_argument("--batched", action="store_true", help="also run the 512-product batched workload")
     ap.add_argument("--amg", action="store_true", help="also run the AMG Galerkin chain")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
-    ap.add_argument("--profile-command", default="", help="the profiled command, recorded in the summaries")
+    ap.add_argument("--profile-command", default="", help="the kernel-trace command, recorded in the summaries")
+    ap.add_argument("--pmc-command", default="",
+                    help="the counter command, with {COUNTER} and {KIND} for FETCH_SIZE/fetch and WRITE_SIZE/write")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command)
+        summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command,
+                           args.pmc_command)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding).",
+        print("bench.py runs on one GPU only: the product has no multi-GPU path; "
+              "value is one GPU's throughput.",
               file=sys.stderr)
         sys.exit(2)
 
