@@ -6,7 +6,8 @@ it (merging adds tuples with equal row and column, Section 2.2), so
 cancelled sums stay stored.  The pins below fix that definition from
 outside the oracle:
 
-* a hand-worked 3x3 example (integer arithmetic done by hand);
+* hand-worked examples stored under tests/golden/ (a 3x3 product and a
+  cancellation, integer arithmetic done by hand);
 * brute force by pure-Python loops in ascending k on tiny random inputs,
   including empty / full rows and columns, rectangular shapes, stored zeros
   and cancellation (structure and bit-exact values);
@@ -21,6 +22,8 @@ outside the oracle:
   output (a dropped term, a flipped sign, a transposed operand, a lost
   structural zero) must each fail a pin.
 """
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -83,34 +86,41 @@ def _matches_bruteforce(c: dict, a: Csx, b: Csx) -> bool:
     return all(got[key] == want[key] or (np.isnan(got[key]) and np.isnan(want[key])) for key in want)
 
 
-def test_hand_worked_example(oracle_mod):
-    # A (3x3), B (3x3), worked by hand:
-    #   A = [[1, 0, 2],      B = [[0, 3, 0],
-    #        [0, 4, 0],           [5, 0, 0],
-    #        [6, 0,-3]]           [0, 1, 7]]
-    # C = A*B:
-    #   row 0: col 1: 1*3 + 2*1 = 5 ; col 2: 2*7 = 14
-    #   row 1: col 0: 4*5 = 20
-    #   row 2: col 1: 6*3 + (-3)*1 = 15 ; col 2: (-3)*7 = -21
-    dense_a = np.array([[1, 0, 2], [0, 4, 0], [6, 0, -3]], float)
-    dense_b = np.array([[0, 3, 0], [5, 0, 0], [0, 1, 7]], float)
-    a = _from_dense(dense_a, "csc")
-    b = _from_dense(dense_b, "csr")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _read_golden(name):
+    """Parse a hand-worked fixture: dense A and B, then C's CSR and facts."""
+    sections, cur = {}, None
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            head, *rest = line.split()
+            if head in ("A", "B") and not rest:
+                cur = sections.setdefault(head, [])
+            elif head in ("rowptr", "colidx", "val", "absval", "flop"):
+                sections[head] = [float(x) for x in rest]
+                cur = None
+            else:
+                cur.append([float(x) for x in line.split()])
+    return sections
+
+
+@pytest.mark.parametrize("name", ["hand_worked_3x3.txt", "cancellation_1x2.txt"])
+def test_hand_worked_golden(oracle_mod, name):
+    g = _read_golden(name)
+    a = _from_dense(np.array(g["A"]), "csc")
+    b = _from_dense(np.array(g["B"]), "csr")
     c = oracle_mod.spgemm(a, b)
     _check_csr_canonical(c)
-    assert list(c["rowptr"]) == [0, 2, 3, 5]
-    assert list(c["colidx"]) == [1, 2, 0, 1, 2]
-    assert list(c["val"]) == [5.0, 14.0, 20.0, 15.0, -21.0]
-    assert c["flop"] == 2 * 1 + 1 * 1 + 2 * 2  # k=0: 2x1, k=1: 1x1, k=2: 2x2
-
-
-def test_hand_worked_cancellation_stays_stored(oracle_mod):
-    # A = [[1, 1]], B = [[1], [-1]] -> C = [[0]] with one stored entry.
-    a = _from_dense(np.array([[1.0, 1.0]]), "csc")
-    b = _from_dense(np.array([[1.0], [-1.0]]), "csr")
-    c = oracle_mod.spgemm(a, b)
-    assert list(c["rowptr"]) == [0, 1] and list(c["colidx"]) == [0] and c["val"][0] == 0.0
-    assert c["absval"][0] == 2.0
+    assert list(c["rowptr"]) == [int(x) for x in g["rowptr"]]
+    assert list(c["colidx"]) == [int(x) for x in g["colidx"]]
+    assert list(c["val"]) == g["val"]
+    if "absval" in g:
+        assert list(c["absval"]) == g["absval"]
+    assert c["flop"] == int(g["flop"][0])
 
 
 def _from_dense(d: np.ndarray, fmt: str, keep_zero_mask=None) -> Csx:
