@@ -85,11 +85,16 @@ typedef struct {
 
 /* Tuning knobs; 0 selects the default.
  *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096
- *   expand_chunk  tuples per expand wave: 512, 1024 or 2048 */
+ *   expand_chunk  tuples per expand wave: 512, 1024 or 2048
+ *   round_tuples  upper bound on tuples per round (0 = no bound): the rows of
+ *                 C are cut into rounds of consecutive bins so that one
+ *                 round's tuples fit the workspace (a single bin larger than
+ *                 the bound is a round by itself) */
 typedef struct {
     int32_t tile_tuples;
     int32_t expand_chunk;
-    int32_t reserved[6];
+    int64_t round_tuples;
+    int32_t reserved[4];
 } pb_tune;
 
 /* Plan facts (host copy, filled by the symbolic step). */
@@ -127,6 +132,14 @@ pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision
                           size_t *workspace_bytes);
 
 /*
+ * Rows wider than the tile.  A row of C whose tuples exceed tile_tuples is
+ * split after the expand into windows of consecutive columns (2^12 columns
+ * while n <= 2^22); every window is sorted and compressed like a row, or, when
+ * it alone exceeds the tile, summed in LDS by a dense accumulator (tuples
+ * added in double; FP32C rounds the double sum to float).  A window that
+ * exceeds the tile while being wider than 2^12 columns (n > 2^22 and heavily
+ * clustered columns) makes the numeric step return PB_ERR_UNSUPPORTED.
+ *
  * Numeric step (Algorithm 2: expand into bins, sort and compress each bin,
  * ConvertCSR).  A_csc / B_csr must be the matrices given to the symbolic
  * step (same arrays and contents).  workspace holds at least the reported
@@ -141,6 +154,30 @@ pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision
 pb_status spgemm_numeric(pb_plan *plan, const pb_csx *A_csc, const pb_csx *B_csr,
                          void *workspace, size_t workspace_bytes, pb_csr_out *C,
                          int64_t *nnzC, void *hip_stream);
+
+/*
+ * Row-range rounds (the paper's partitioned formulation for products whose
+ * expanded tuples exceed memory, Sections 2.2 and 3.4).  A plan built with
+ * tune->round_tuples > 0 and more tuples than that, or with rows wider than
+ * the tile, runs as rounds of consecutive rows.  spgemm_numeric then runs
+ * every round in turn into one C (the workspace is reused); the calls below
+ * let a caller take C one round at a time instead, when all of C does not
+ * fit.  Plans of one round report one round covering every row.
+ *
+ * spgemm_plan_rounds: *nrounds receives the number of rounds; row_begin
+ * (nrounds+1 entries, may be NULL) the first row of each round and m at the
+ * end; flop_per_round (nrounds entries, may be NULL) each round's tuples,
+ * which bound its nnz(C).  Pass NULL arrays first to learn nrounds.
+ *
+ * spgemm_numeric_round: computes rows [row_begin[r], row_begin[r+1]) of C
+ * into C, whose rowptr then has row_begin[r+1]-row_begin[r]+1 entries
+ * starting at 0 and whose colidx / val hold that round's entries.  Same
+ * workspace, synchronisation and error rules as spgemm_numeric.
+ */
+pb_status spgemm_plan_rounds(const pb_plan *plan, int64_t *nrounds, int64_t *row_begin, int64_t *flop_per_round);
+pb_status spgemm_numeric_round(pb_plan *plan, const pb_csx *A_csc, const pb_csx *B_csr, int64_t round,
+                               void *workspace, size_t workspace_bytes, pb_csr_out *C, int64_t *nnzC,
+                               void *hip_stream);
 
 /*
  * Batched products C_i = A_i * B_i, i < count, of uneven sizes (a workload
@@ -178,13 +215,14 @@ const char *spgemm_last_error(void);
 
 /* ---------------- measurement support ----------------
  * Kernel timing with HIP events recorded on the launch stream around the
- * library's own kernels.  Phases: 0 symbolic (all its kernels), 1 expand,
- * 2 sort+compress (one fused kernel), 3 entries per row of C and the
- * row-pointer scan.
+ * library's own kernels.  Phases: 0 symbolic (all its kernels), 1 expand
+ * (with a round's restriction of A's columns), 2 sort+compress (and the
+ * dense windows' output), 3 entries per row of C and the row-pointer scan,
+ * 4 the partition of wide rows into column windows.
  * spgemm_profile_begin clears the accumulators and turns recording on;
  * spgemm_profile_end waits for the recorded events, turns recording off and
  * returns, per phase, the summed milliseconds and the number of launches. */
-#define PB_NPHASES 4
+#define PB_NPHASES 5
 typedef struct {
     double ms[PB_NPHASES];
     int64_t launches[PB_NPHASES];

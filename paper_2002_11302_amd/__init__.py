@@ -124,6 +124,7 @@ def _tune(tune):
     t = _b.PbTune()
     t.tile_tuples = int(tune.get("tile_tuples", 0))
     t.expand_chunk = int(tune.get("expand_chunk", 0))
+    t.round_tuples = int(tune.get("round_tuples", 0))
     return ctypes.byref(t)
 
 
@@ -162,6 +163,36 @@ def spgemm_numeric(plan: Plan, A: DeviceCsx, B: DeviceCsx, workspace, C_rowptr, 
     wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _b.check(lib.spgemm_numeric(plan.handle, ctypes.byref(a), ctypes.byref(b), wsp, wsb, ctypes.byref(out),
                                 ctypes.byref(nnz) if sync else None, _stream(stream)), "spgemm_numeric")
+    return int(nnz.value) if sync else None
+
+
+def spgemm_plan_rounds(plan: Plan):
+    """(row_begin, flop_per_round): round r computes rows
+    [row_begin[r], row_begin[r+1]) of C and expands flop_per_round[r] tuples."""
+    lib = _b.lib()
+    n = ctypes.c_int64(0)
+    _b.check(lib.spgemm_plan_rounds(plan.handle, ctypes.byref(n), None, None), "spgemm_plan_rounds")
+    rb = (ctypes.c_int64 * (n.value + 1))()
+    fl = (ctypes.c_int64 * max(n.value, 1))()
+    _b.check(lib.spgemm_plan_rounds(plan.handle, ctypes.byref(n), rb, fl), "spgemm_plan_rounds")
+    return [int(x) for x in rb], [int(fl[i]) for i in range(n.value)]
+
+
+def spgemm_numeric_round(plan: Plan, A: DeviceCsx, B: DeviceCsx, round_index: int, workspace, C_rowptr, C_colidx,
+                         C_val, sync: bool = True, stream=None):
+    """Rows of one round of C into caller tensors (row pointers start at 0).
+    Returns the round's nnz when ``sync``."""
+    lib = _b.lib()
+    a, b = A._abi(), B._abi()
+    cap = int(C_colidx.numel())
+    out = _b.PbCsrOut(C_rowptr.data_ptr(), C_colidx.data_ptr() if cap else None,
+                      C_val.data_ptr() if cap else None, cap)
+    nnz = ctypes.c_int64(-1)
+    wsp = workspace.data_ptr() if workspace is not None and workspace.numel() else None
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _b.check(lib.spgemm_numeric_round(plan.handle, ctypes.byref(a), ctypes.byref(b), int(round_index), wsp, wsb,
+                                      ctypes.byref(out), ctypes.byref(nnz) if sync else None, _stream(stream)),
+             "spgemm_numeric_round")
     return int(nnz.value) if sync else None
 
 

@@ -18,8 +18,8 @@ STATUS_NAMES = {
     5: "PB_ERR_CAPACITY", 6: "PB_ERR_HIP", 7: "PB_ERR_UNSUPPORTED", 8: "PB_ERR_INTERNAL",
 }
 PRECISIONS = {"f64": 0, "f32c": 1}
-PB_NPHASES = 4
-PHASES = ("symbolic", "expand", "sort_compress", "row_counts")
+PB_NPHASES = 5
+PHASES = ("symbolic", "expand", "sort_compress", "row_counts", "wide_partition")
 
 
 class PbError(RuntimeError):
@@ -42,7 +42,8 @@ class PbCsrOut(ctypes.Structure):
 
 
 class PbTune(ctypes.Structure):
-    _fields_ = [("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("round_tuples", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class PbPlanInfo(ctypes.Structure):
@@ -70,6 +71,9 @@ SIGNATURES = {
     "spgemm_numeric": (ctypes.c_int, [_vp, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx), _vp, _sz,
                                       ctypes.POINTER(PbCsrOut), ctypes.POINTER(_i64), _vp]),
     "spgemm_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(PbPlanInfo)]),
+    "spgemm_plan_rounds": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "spgemm_numeric_round": (ctypes.c_int, [_vp, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx), _i64, _vp, _sz,
+                                            ctypes.POINTER(PbCsrOut), ctypes.POINTER(_i64), _vp]),
     "spgemm_plan_destroy": (None, [_vp]),
     "spgemm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "spgemm_last_error": (ctypes.c_char_p, []),

@@ -13,6 +13,8 @@ enum : uint32_t {
     kErrBinOverflow = 2u,  // an expand append ran past its bin (inconsistent inputs)
     kErrCapacity = 4u,  // C had less room than nnz(C)
     kErrTile = 8u,      // a bin larger than the sort tile reached the sort kernel
+    kErrWide = 16u,     // a wide row's column window exceeds the tile and the dense accumulator
+    kErrGrid = 32u,     // more bins than the launch bound (internal)
 };
 
 // Upper bound on look-back polls before a wait is abandoned with kErrSpin;

@@ -177,6 +177,7 @@ struct BinSrc {
     int rowbits;
     const int64_t *prob_row0;  // batched: sorted first rows of the problems (or null)
     int64_t nprob;
+    int seg_log;               // >= 0: a bin also starts at every multiple of 2^seg_log
     __device__ uint64_t operator()(int64_t r) const {
         const uint64_t thalf = T / 2;
         const uint64_t H = T - info->maxnormal;
@@ -198,6 +199,7 @@ struct BinSrc {
                 int64_t j = last_le(prob_row0, 0, nprob, (int64_t)r);
                 start = prob_row0[j] == r;
             }
+            if (!start && seg_log >= 0) start = (r & ((1ll << seg_log) - 1)) == 0;
         }
         return start ? ((1ull << 31) | (uint64_t)r) : 0;
     }
@@ -218,6 +220,7 @@ struct BinDst {
     int64_t m;
     uint64_t T;
     SymInfo *info;
+    int32_t *oversize;  // rows with more than T tuples are listed here (or only counted)
     __device__ void operator()(int64_t r, uint64_t excl, uint64_t e) const {
         const uint64_t incl = BinOp::combine(excl, e);
         const uint64_t bin = (incl >> 31) - 1;
@@ -230,7 +233,10 @@ struct BinDst {
         if (e) {
             binrow0[bin] = (int32_t)r;
             binoff[bin] = (int64_t)R[r];
-            if (R[r + 1] - R[r] > T) atomic_add_agent(&info->noversize, (uint64_t)1);
+            if (R[r + 1] - R[r] > T) {
+                const uint64_t slot = atomic_add_agent(&info->noversize, (uint64_t)1);
+                if (oversize) oversize[slot] = (int32_t)r;
+            }
         }
     }
     __device__ void total(uint64_t t) const {
@@ -280,6 +286,8 @@ struct ExpandArgs {
     void *vals;
     int cb;
     uint32_t *err;
+    const int64_t *astart;  // rounds: first entry of A(:,k) in the round's rows (null: all of A(:,k))
+    int64_t slot0;          // rounds: slot of the round's first tuple
 };
 
 // (q, r) = divmod(x, d) for 0 <= x, 1 <= d; float reciprocal with an exact
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
         const int64_t Fk = a.F[k];
         const int64_t bs = a.brp[k];
         const int64_t nb = a.brp[k + 1] - bs;
-        const int64_t as = a.acp[k];
+        const int64_t as = a.astart ? a.astart[k] : a.acp[k];
         const int64_t seg_end = Fk1 < t1 ? Fk1 : t1;
         // four 64-tuple steps per iteration, every load issued before use
         constexpr int U = 4;
@@ -367,9 +375,9 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
-                    const int64_t slot = rt[u].base + (int64_t)rp[u] + jj[u];
+                    const int64_t slot = rt[u].base - a.slot0 + (int64_t)rp[u] + jj[u];
                     const uint32_t key = (rt[u].rl << a.cb) | col[u];
-                    if (slot < a.flop) {
+                    if ((uint64_t)slot < (uint64_t)a.flop) {
                         a.keys[slot] = key;
                         vals[slot] = (VT)(av[u] * bvv[u]);
                     } else {
@@ -387,8 +395,9 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
 // ConvertCSR, part 1: entries per row of C.  The tuple array is in row
 // order (each row's tuples are contiguous), so nnz(C(r,:)) is the number of
 // distinct keys among row r's tuples.  One workgroup per bin inserts the
-// bin's keys into an LDS hash set (open addressing, linear probing); the
-// first insertion of a key counts for its row.  Only keys are read.
+// bin's keys into an LDS hash set (open addressing, linear probing); once
+// every key is in, each occupied slot adds one to its key's row.  Only keys
+// are read.
 struct CountArgs {
     const int32_t *binrow0;
     const int64_t *binoff;
@@ -396,6 +405,11 @@ struct CountArgs {
     int cb;
     uint32_t *rownnz;
     uint32_t *err;
+    int64_t T;                 // bins with more tuples are wide and done elsewhere
+    int64_t bin0;              // first bin of the launch
+    int64_t slot0;             // slot of the launch's first tuple in `keys`
+    int64_t row_base;          // rownnz is indexed by row - row_base
+    const uint64_t *nbins;     // if set, blocks at or past *nbins exit
 };
 
 template <int BLOCK, int TMAX>
@@ -407,11 +421,18 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     __shared__ uint32_t table[TS];
     __shared__ uint32_t rowcnt[TMAX];
     __shared__ uint32_t s_special;
-    const int64_t b = blockIdx.x;
+    if (a.nbins) {
+        const uint64_t nb = *a.nbins;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && nb > gridDim.x) atomic_or_agent(a.err, (uint32_t)kErrGrid);
+        if ((uint64_t)blockIdx.x >= nb) return;
+    }
+    const int64_t b = a.bin0 + blockIdx.x;
     const int64_t row0 = a.binrow0[b];
     const int nrows = (int)(a.binrow0[b + 1] - row0);
-    const int64_t toff = a.binoff[b];
-    int N = (int)(a.binoff[b + 1] - toff);
+    const int64_t toff = a.binoff[b] - a.slot0;
+    const int64_t N64 = a.binoff[b + 1] - a.binoff[b];
+    if (N64 > a.T) return;
+    int N = (int)N64;
     if (N > TMAX || nrows > TMAX) {
         if (threadIdx.x == 0) atomic_or_agent(a.err, (uint32_t)kErrTile);
         return;
@@ -430,12 +451,10 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
         const int p = i * BLOCK + threadIdx.x;
         kr[i] = p < N ? gk[p] : EMPTY;
     }
-    const uint32_t lane = lane_id();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const uint32_t key = kr[i];
         const int p = i * BLOCK + threadIdx.x;
-        bool fresh = false;
         if (p < N) {
             if (key == EMPTY) {  // the one key equal to the empty marker
                 s_special = 1;
@@ -443,35 +462,23 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
                 uint32_t h = (key * 0x9E3779B1u) >> (32 - LOG_TS);
                 while (true) {
                     const uint32_t old = atomicCAS(&table[h], EMPTY, key);
-                    if (old == EMPTY) {
-                        fresh = true;
-                        break;
-                    }
-                    if (old == key) break;
+                    if (old == EMPTY || old == key) break;
                     h = (h + 1) & (TS - 1);
                 }
             }
         }
-        // Consecutive lanes hold consecutive tuples, which mostly share a
-        // row: count the fresh keys per run of equal rows within the wave
-        // and let the first lane of each run add the count.
-        const uint32_t row = (p < N && cb < 32) ? (key >> cb) : 0xffffffffu;
-        const uint32_t prev = __shfl_up(row, 1u, kWave);
-        const bool seg_head = (lane == 0) || (row != prev);
-        const uint64_t heads = ballot(seg_head);
-        const uint64_t freshm = ballot(fresh);
-        if (seg_head && row != 0xffffffffu) {
-            const uint64_t above = heads & ~((2ull << lane) - 1);  // heads after this lane
-            const uint32_t end = above ? (uint32_t)__builtin_ctzll(above) : 64u;
-            const uint64_t segm = (end >= 64 ? ~0ull : ((1ull << end) - 1)) & ~((1ull << lane) - 1);
-            const uint32_t cnt = popc64(freshm & segm);
-            if (cnt) atomicAdd(&rowcnt[row], cnt);
-        }
+    }
+    __syncthreads();
+    // Slots hold the bin's distinct keys in hash order, so neighbouring
+    // lanes mostly hit different rows' counters.
+    for (int x = threadIdx.x; x < TS; x += BLOCK) {
+        const uint32_t key = table[x];
+        if (key != EMPTY) atomicAdd(&rowcnt[cb < 32 ? (key >> cb) : 0u], 1u);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_special) rowcnt[cb < 32 ? (EMPTY >> cb) : 0u] += 1;
     __syncthreads();
-    for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 + x] = rowcnt[x];
+    for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 - a.row_base + x] = rowcnt[x];
 }
 
 // rowptr = exclusive scan of the per-row entry counts (rowptr[m] = nnz(C)).
@@ -482,8 +489,10 @@ struct RowNnzSrc {
 struct RowPtrDst : NoSide {
     int64_t *rowptr;
     int64_t m;
-    __device__ void operator()(int64_t r, uint64_t excl, uint64_t) const { rowptr[r] = (int64_t)excl; }
-    __device__ void total(uint64_t t) const { rowptr[m] = (int64_t)t; }
+    const int64_t *base;  // rounds writing one C: entries before the round (or null)
+    __device__ int64_t b0() const { return base ? *base : 0; }
+    __device__ void operator()(int64_t r, uint64_t excl, uint64_t) const { rowptr[r] = b0() + (int64_t)excl; }
+    __device__ void total(uint64_t t) const { rowptr[m] = b0() + (int64_t)t; }
 };
 
 // ---------------------------------------------------------------------------
@@ -605,6 +614,13 @@ struct SortArgs {
     const OutDesc *outs;
     const int64_t *prob_row0;
     int nprob;
+    int64_t T;              // bins with more tuples are wide and done elsewhere
+    int64_t bin0;           // first bin of the launch
+    int64_t slot0;          // slot of the launch's first tuple in `keys` / `vals`
+    int64_t row_base;       // rowptr is indexed by row - row_base
+    const uint64_t *nbins;  // if set, blocks at or past *nbins exit
+    int vshift;             // virtual rows of wide rows: column = (row & vmask) << vshift | key column
+    uint32_t vmask;
 };
 
 template <class VT>
@@ -670,11 +686,14 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     const int cb = a.cb;
     const uint32_t colmask = cb ? ((1u << cb) - 1u) : 0u;
 
-    const int64_t b = blockIdx.x;
+    if (a.nbins && (int64_t)blockIdx.x >= (int64_t)*a.nbins) return;
+    const int64_t b = a.bin0 + blockIdx.x;
     const int64_t row0 = a.binrow0[b];
     const int64_t nrows = a.binrow0[b + 1] - row0;
-    const int64_t toff = a.binoff[b];
-    int N = (int)(a.binoff[b + 1] - toff);
+    const int64_t toff = a.binoff[b] - a.slot0;
+    const int64_t N64 = a.binoff[b + 1] - a.binoff[b];
+    if (N64 > a.T) return;
+    int N = (int)N64;
     if (N > TMAX) {
         if (threadIdx.x == 0) atomic_or_agent(a.err, (uint32_t)kErrTile);
         return;
@@ -691,7 +710,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         cvals = od.val;
         capacity = od.capacity;
     } else {
-        base = a.rowptr[row0];
+        base = a.rowptr[row0 - a.row_base];
     }
     const uint32_t *gk = a.keys + toff;
     const VT *gvb = (const VT *)a.vals + toff;
@@ -922,7 +941,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
             for (int q = p + 1; q < N && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
             const int64_t out = base + wbase + hr[i];
             if (out < capacity) {
-                colidx[out] = (int32_t)(key & colmask);
+                const uint32_t vcol =
+                    a.vshift ? ((((uint32_t)row0 + (key >> cb)) & a.vmask) << a.vshift) : 0u;
+                colidx[out] = (int32_t)(vcol | (key & colmask));
                 cv[out] = mg.result();
             } else {
                 atomic_or_agent(a.err, (uint32_t)kErrCapacity);

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "pb_big.h"
 #include "pb_kernels.h"
 
 using namespace pb;
@@ -134,10 +135,13 @@ int col_bits(int64_t n) {
     return 64 - __builtin_clzll((uint64_t)(n - 1));
 }
 
-pb_status resolve_tune(const pb_tune *t, int *T, int *chunk) {
+pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tuples) {
     *T = kDefaultTile;
     *chunk = kDefaultChunk;
+    *round_tuples = 0;
     if (!t) return PB_OK;
+    if (t->round_tuples < 0) return fail(PB_ERR_ARG, "round_tuples must be >= 0");
+    *round_tuples = t->round_tuples;
     if (t->tile_tuples) {
         if (t->tile_tuples < 256 || t->tile_tuples > kSortTmax)
             return fail(PB_ERR_ARG, "tile_tuples must be in [256, %d]", kSortTmax);
@@ -158,6 +162,7 @@ struct pb_plan {
     // the (block-diagonal, for a batch) product: C is m x n, inner dimension k
     int64_t m = 0, k = 0, n = 0, nnzA = 0, nnzB = 0;
     int32_t count = 1;  // problems in the device tables (1 for a single product)
+    int64_t round_tuples = 0;  // requested tuple budget per round (0: no limit)
     int32_t user_count = 1;
     pb_precision prec = PB_F64;
     int T = kDefaultTile, chunk = kDefaultChunk, cb = 0;
@@ -183,6 +188,18 @@ struct pb_plan {
     SymInfo h{};
     int64_t nchunks = 0;
     size_t ws_bytes = 0;
+    // rounds and wide rows (single products whose tuples exceed the round
+    // budget, or that have rows wider than the tile)
+    bool rounds_mode = false;
+    int wbits = 0, lognwin = 0;
+    struct Round {
+        int64_t r0 = 0, r1 = 0, b0 = 0, b1 = 0;  // rows and bins of the round
+        int64_t slot0 = 0, flop = 0;              // first slot (R[r0]) and tuples
+        int64_t nbig = 0, bigflop = 0, nchunks = 0, nvirt = 0, nvbins = 0, ndense = 0;
+        size_t stage_off = 0, stage_bytes = 0;    // wide-row tables in the pinned staging area
+        size_t ws_bytes = 0;
+    };
+    std::vector<Round> rounds;
     ~pb_plan() {
         if (pinned) (void)hipHostFree(pinned);
     }
@@ -307,9 +324,338 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
         PB_TRY(launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(p->T / 2), L.info}, L.stR,
                                   &L.tickets[1], &L.info->err, st, "row scan"));
         PB_TRY(launch_scan<BinOp>(
-            m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count},
-            BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info}, L.stB, &L.tickets[2], &L.info->err, st,
+            m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count, -1},
+            BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2], &L.info->err, st,
             "bin scan"));
+    }
+    return PB_OK;
+}
+
+// Sort + compress launch for `nbins` bins (the tile picks the kernel shape).
+pb_status launch_sort(const pb_plan *p, const SortArgs &sa, int64_t nbins, hipStream_t st) {
+    const bool f64 = p->prec == PB_F64;
+    if (p->T <= kSortTmaxSmall) {
+        if (f64)
+            hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins),
+                               dim3(kSortBlockSmall), 0, st, sa);
+        else
+            hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins),
+                               dim3(kSortBlockSmall), 0, st, sa);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins),
+                               dim3(kSortBlock), 0, st, sa);
+        else
+            hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins),
+                               dim3(kSortBlock), 0, st, sa);
+    }
+    PB_LAUNCHED("sort+compress");
+    return PB_OK;
+}
+
+// ---- rounds and wide rows ---------------------------------------------------
+pb_status ensure_pinned(pb_plan *p, size_t bytes);
+
+// Device layout of one round's numeric workspace.  The zeroed region comes
+// first; the wide-row tables (bigs, bige, cpre, bigr) are one block, in the
+// order of the pinned staging copy.
+struct RoundLayout {
+    uint32_t *tickets;  // [0] rows, [1] columns, [2] virtual rows, [3] virtual bins
+    uint32_t *err;
+    SymInfo *rinfo, *vinfo;
+    uint64_t *st_rows, *st_cols, *st_v, *st_vb;
+    uint32_t *cnt_v, *cur_v;
+    size_t zero_bytes;
+    int64_t *astart;
+    uint64_t *colflop;
+    int64_t *F;
+    int32_t *kstart;
+    uint32_t *rownnz;
+    char *bigtab;
+    int64_t *bigs, *bige, *cpre;
+    int32_t *bigr;
+    uint32_t *chist;
+    uint64_t *Rv;
+    RowTab *vrowtab;
+    int32_t *vbinrow0;
+    int64_t *vbinoff;
+    int32_t *dense;
+    uint32_t *rownnz_v;
+    int64_t *rowptr_v;
+    uint32_t *keys2;
+    void *vals2;
+    uint32_t *keys;
+    void *vals;
+    size_t total;
+};
+
+size_t big_tables_bytes(int64_t nbig) {
+    Carver cv(nullptr);
+    cv.take<int64_t>(nbig);
+    cv.take<int64_t>(nbig);
+    cv.take<int64_t>(nbig + 1);
+    cv.take<int32_t>(nbig);
+    return cv.mark();
+}
+
+RoundLayout round_layout(void *base, const pb_plan *p, const pb_plan::Round &rd) {
+    Carver cv(base);
+    RoundLayout L{};
+    const bool partial = rd.r0 > 0 || rd.r1 < p->m;
+    const int64_t nrows = rd.r1 - rd.r0;
+    const int vb = p->prec == PB_F64 ? 8 : 4;
+    L.tickets = cv.take<uint32_t>(5);
+    L.err = L.tickets + 4;
+    L.rinfo = cv.take<SymInfo>(1);
+    L.vinfo = cv.take<SymInfo>(1);
+    L.st_rows = cv.take<uint64_t>(ceil_div(nrows, kScanTile) + 1);
+    L.st_cols = cv.take<uint64_t>(partial ? ceil_div(p->k, kScanTile) + 1 : 0);
+    L.st_v = cv.take<uint64_t>(ceil_div(rd.nvirt, kScanTile) + 1);
+    L.st_vb = cv.take<uint64_t>(ceil_div(rd.nvirt, kScanTile) + 1);
+    L.cnt_v = cv.take<uint32_t>(rd.nvirt);
+    L.cur_v = cv.take<uint32_t>(rd.nvirt);
+    L.zero_bytes = cv.mark();
+    L.astart = cv.take<int64_t>(partial ? p->k : 0);
+    L.colflop = cv.take<uint64_t>(partial ? p->k : 0);
+    L.F = cv.take<int64_t>(partial ? p->k + 1 : 0);
+    L.kstart = cv.take<int32_t>(ceil_div(rd.flop, p->chunk) + 1);
+    L.rownnz = cv.take<uint32_t>(nrows);
+    L.bigtab = cv.take<char>((int64_t)(rd.nbig ? big_tables_bytes(rd.nbig) : 0));
+    if (rd.nbig) {
+        Carver tc(L.bigtab);
+        L.bigs = tc.take<int64_t>(rd.nbig);
+        L.bige = tc.take<int64_t>(rd.nbig);
+        L.cpre = tc.take<int64_t>(rd.nbig + 1);
+        L.bigr = tc.take<int32_t>(rd.nbig);
+    }
+    L.chist = cv.take<uint32_t>(rd.nchunks << p->lognwin);
+    L.Rv = cv.take<uint64_t>(rd.nbig ? rd.nvirt + 1 : 0);
+    L.vrowtab = cv.take<RowTab>(rd.nvirt);
+    L.vbinrow0 = cv.take<int32_t>(rd.nbig ? rd.nvirt + 1 : 0);
+    L.vbinoff = cv.take<int64_t>(rd.nbig ? rd.nvirt + 1 : 0);
+    L.dense = cv.take<int32_t>(rd.ndense);
+    L.rownnz_v = cv.take<uint32_t>(rd.nvirt);
+    L.rowptr_v = cv.take<int64_t>(rd.nbig ? rd.nvirt + 1 : 0);
+    L.keys2 = cv.take<uint32_t>(rd.bigflop);
+    L.vals2 = cv.take<char>(rd.bigflop * vb);
+    L.keys = cv.take<uint32_t>(rd.flop);
+    L.vals = cv.take<char>(rd.flop * vb);
+    L.total = cv.mark();
+    return L;
+}
+
+// Cut the bins into rounds (consecutive bins, at most round_tuples tuples
+// each unless one bin alone is larger) and list every round's wide rows.
+// Reads the bin tables back once.
+pb_status build_rounds(pb_plan *p, hipStream_t st) {
+    const int64_t nbins = (int64_t)p->h.nbins;
+    std::vector<int32_t> brow(nbins + 1);
+    std::vector<int64_t> boff(nbins + 1);
+    PB_HIP(hipMemcpyAsync(brow.data(), p->binrow0, sizeof(int32_t) * (nbins + 1), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipMemcpyAsync(boff.data(), p->binoff, sizeof(int64_t) * (nbins + 1), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    p->rounds_mode = true;
+    p->lognwin = std::max(0, std::min(kMaxLogWin, p->cb - kDenseBits));
+    p->wbits = p->cb - p->lognwin;
+    const int64_t budget = p->round_tuples > 0 ? p->round_tuples : INT64_MAX;
+    const int64_t T = p->T;
+    const int64_t vmax = (int64_t)1 << 30;  // virtual rows per round (32-bit bin tables)
+    p->rounds.clear();
+    int64_t b = 0;
+    while (b < nbins) {
+        pb_plan::Round rd;
+        rd.b0 = b;
+        int64_t acc = 0, nb = 0;
+        while (b < nbins) {
+            const int64_t sz = boff[b + 1] - boff[b];
+            const int64_t nbw = nb + (sz > T ? 1 : 0);
+            if (b > rd.b0 && (acc + sz > budget || (nbw << p->lognwin) > vmax)) break;
+            acc += sz;
+            nb = nbw;
+            ++b;
+        }
+        rd.b1 = b;
+        rd.r0 = brow[rd.b0];
+        rd.r1 = brow[rd.b1];
+        rd.slot0 = boff[rd.b0];
+        rd.flop = acc;
+        rd.nbig = nb;
+        p->rounds.push_back(rd);
+    }
+    if (p->rounds.empty()) {  // no rows: one empty round keeps the code paths uniform
+        pb_plan::Round rd;
+        p->rounds.push_back(rd);
+    }
+    // wide-row tables, staged once in pinned memory
+    size_t stage = 0;
+    for (auto &rd : p->rounds) {
+        rd.stage_off = stage;
+        rd.stage_bytes = rd.nbig ? big_tables_bytes(rd.nbig) : 0;
+        stage += rd.stage_bytes;
+    }
+    if (stage) PB_TRY(ensure_pinned(p, stage));
+    size_t ws = 0;
+    for (auto &rd : p->rounds) {
+        if (rd.nbig) {
+            Carver tc((char *)p->pinned + rd.stage_off);
+            int64_t *bigs = tc.take<int64_t>(rd.nbig);
+            int64_t *bige = tc.take<int64_t>(rd.nbig);
+            int64_t *cpre = tc.take<int64_t>(rd.nbig + 1);
+            int32_t *bigr = tc.take<int32_t>(rd.nbig);
+            int64_t i = 0;
+            cpre[0] = 0;
+            for (int64_t bb = rd.b0; bb < rd.b1; ++bb) {
+                const int64_t sz = boff[bb + 1] - boff[bb];
+                if (sz <= T) continue;
+                bigs[i] = boff[bb] - rd.slot0;
+                bige[i] = boff[bb + 1] - rd.slot0;
+                bigr[i] = brow[bb];
+                cpre[i + 1] = cpre[i] + ceil_div(sz, kBigChunk);
+                rd.bigflop += sz;
+                ++i;
+            }
+            rd.nchunks = cpre[rd.nbig];
+            rd.nvirt = rd.nbig << p->lognwin;
+            // virtual bins: every bin but the segment and oversize starts spans at
+            // least T/2 of weight (tuples + rows); oversize rows have > T tuples
+            // (floor(weight / H) changes: weight <= tuples + 2 per row, H >= T/2;
+            // rows over T/2 start a bin and make their successor start one)
+            const int64_t over = rd.bigflop / (T + 1) + 1;
+            const int64_t bound = (6 * rd.bigflop + 4 * rd.nvirt) / T + rd.nbig + 4;
+            rd.nvbins = std::min(rd.nvirt, bound);
+            rd.ndense = std::min(rd.nvirt, over);
+        }
+        rd.ws_bytes = round_layout(nullptr, p, rd).total;
+        ws = std::max(ws, rd.ws_bytes);
+    }
+    p->ws_bytes = ws;
+    return PB_OK;
+}
+
+// One round: rows [r0, r1) of C.  rowptr_out is indexed by row - r0 and has
+// r1 - r0 + 1 entries; rowptr_base (or null for 0) holds the number of
+// entries of C before the round; colidx / cval are indexed by C position.
+pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx *A, const pb_csx *B,
+                    int64_t *rowptr_out, const int64_t *rowptr_base, int32_t *colidx, void *cval, int64_t capacity,
+                    hipStream_t st) {
+    const RoundLayout L = round_layout(ws, p, rd);
+    const bool f64 = p->prec == PB_F64;
+    const bool partial = rd.r0 > 0 || rd.r1 < p->m;
+    const int64_t nrows = rd.r1 - rd.r0;
+    const int64_t K = p->k;
+    PB_TRY(fill_zero(ws, L.zero_bytes, st));
+    if (rd.nbig)
+        PB_HIP(hipMemcpyAsync(L.bigtab, (char *)p->pinned + rd.stage_off, rd.stage_bytes, hipMemcpyHostToDevice, st));
+    const int64_t *F = p->F;
+    const int64_t *astart = nullptr;
+    const int64_t nchunks = ceil_div(rd.flop, p->chunk);
+    if (rd.flop > 0) {
+        ProfScope ps(st, 1);
+        if (partial) {
+            hipLaunchKernelGGL(k_round_cols, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, st, K, A->ptr, A->idx,
+                               B->ptr, (int32_t)rd.r0, (int32_t)rd.r1, L.astart, L.colflop);
+            PB_LAUNCHED("round columns");
+            PB_TRY(launch_scan<SumOp>(K, U64Src{L.colflop}, ColFlopDst{{}, L.F, K, L.rinfo}, L.st_cols,
+                                      &L.tickets[1], L.err, st, "round flop scan"));
+            F = L.F;
+            astart = L.astart;
+        }
+        hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(nchunks + 1, 256)), dim3(256), 0, st, nchunks,
+                           (int64_t)p->chunk, K, F, L.kstart);
+        PB_LAUNCHED("chunk start");
+        ExpandArgs ea{rd.flop, K, F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, p->runpos,
+                      p->rowtab, L.keys, L.vals, p->cb, L.err, astart, rd.slot0};
+        const unsigned grid = (unsigned)ceil_div(nchunks, 4);
+        switch (p->chunk) {
+            case 512:
+                if (f64) hipLaunchKernelGGL((k_expand<512, double>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                else hipLaunchKernelGGL((k_expand<512, float>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                break;
+            case 2048:
+                if (f64) hipLaunchKernelGGL((k_expand<2048, double>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                else hipLaunchKernelGGL((k_expand<2048, float>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                break;
+            default:
+                if (f64) hipLaunchKernelGGL((k_expand<1024, double>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                else hipLaunchKernelGGL((k_expand<1024, float>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                break;
+        }
+        PB_LAUNCHED("expand");
+    }
+    const int64_t nb = rd.b1 - rd.b0;
+    const int nwin = 1 << p->lognwin;
+    BigArgs ba{rd.nbig, p->lognwin, p->wbits, p->cb, L.bigs, L.bige, L.cpre, L.keys, L.vals, L.chist, L.cnt_v,
+               L.cur_v, L.Rv, L.vrowtab, L.keys2, L.vals2, rd.bigflop, L.err};
+    if (rd.nbig) {
+        ProfScope ps(st, 4);
+        hipLaunchKernelGGL(k_big_hist<512>, dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
+        PB_LAUNCHED("wide-row histogram");
+        PB_TRY(launch_scan<SumOp>(rd.nvirt, U32Src{L.cnt_v}, RowFlopDst{L.Rv, rd.nvirt, (uint64_t)(p->T / 2), L.vinfo},
+                                  L.st_v, &L.tickets[2], L.err, st, "virtual row scan"));
+        PB_TRY(launch_scan<BinOp>(rd.nvirt,
+                                  BinSrc{L.Rv, L.vinfo, (uint64_t)p->T, 32 - p->wbits, nullptr, 0, p->lognwin},
+                                  BinDst{L.vrowtab, L.vbinrow0, L.vbinoff, L.Rv, rd.nvirt, (uint64_t)p->T, L.vinfo,
+                                         L.dense},
+                                  L.st_vb, &L.tickets[3], L.err, st, "virtual bin scan"));
+        if (f64) hipLaunchKernelGGL((k_big_scatter<512, double>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
+        else hipLaunchKernelGGL((k_big_scatter<512, float>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
+        PB_LAUNCHED("wide-row scatter");
+    }
+    DenseArgs da{L.dense, &L.vinfo->noversize, L.Rv, L.keys2, L.vals2, p->wbits, p->lognwin, L.rownnz_v,
+                 L.rowptr_v, colidx, cval, capacity, L.err};
+    const unsigned dgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rd.ndense, 2048));
+    {
+        ProfScope ps(st, 3);
+        if (nb > 0) {
+            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err, p->T, rd.b0, rd.slot0, rd.r0, nullptr};
+            if (p->T <= kSortTmaxSmall)
+                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)nb), dim3(kCountBlock), 0,
+                                   st, ca);
+            else
+                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmax>), dim3((unsigned)nb), dim3(kCountBlock), 0, st,
+                                   ca);
+            PB_LAUNCHED("row counts");
+        }
+        if (rd.nbig) {
+            CountArgs cv{L.vbinrow0, L.vbinoff, L.keys2, p->wbits, L.rownnz_v, L.err, p->T, 0, 0, 0, &L.vinfo->nbins};
+            if (p->T <= kSortTmaxSmall)
+                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)rd.nvbins),
+                                   dim3(kCountBlock), 0, st, cv);
+            else
+                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmax>), dim3((unsigned)rd.nvbins), dim3(kCountBlock),
+                                   0, st, cv);
+            PB_LAUNCHED("virtual row counts");
+            if (f64) hipLaunchKernelGGL((k_dense<512, double, false>), dim3(dgrid), dim3(512), 0, st, da);
+            else hipLaunchKernelGGL((k_dense<512, float, false>), dim3(dgrid), dim3(512), 0, st, da);
+            PB_LAUNCHED("dense counts");
+            hipLaunchKernelGGL(k_big_rowsum, dim3((unsigned)ceil_div(rd.nbig, 4)), dim3(256), 0, st, rd.nbig,
+                               p->lognwin, L.bigr, rd.r0, L.rownnz_v, L.rownnz);
+            PB_LAUNCHED("wide-row sums");
+        }
+        if (nrows > 0)
+            PB_TRY(launch_scan<SumOp>(nrows, RowNnzSrc{L.rownnz}, RowPtrDst{{}, rowptr_out, nrows, rowptr_base},
+                                      L.st_rows, &L.tickets[0], L.err, st, "row pointer scan"));
+        if (rd.nbig) {
+            hipLaunchKernelGGL(k_big_rowptr, dim3((unsigned)ceil_div(rd.nbig, 4)), dim3(256), 0, st, rd.nbig,
+                               p->lognwin, L.bigr, rd.r0, rowptr_out, L.rownnz_v, L.rowptr_v);
+            PB_LAUNCHED("virtual row pointers");
+        }
+    }
+    {
+        ProfScope ps(st, 2);
+        if (nb > 0) {
+            SortArgs sa{p->binrow0, p->binoff, L.keys, L.vals, p->cb, L.err, rowptr_out, colidx, cval, capacity,
+                        nullptr, nullptr, 1, p->T, rd.b0, rd.slot0, rd.r0, nullptr, 0, 0};
+            PB_TRY(launch_sort(p, sa, nb, st));
+        }
+        if (rd.nbig) {
+            SortArgs sv{L.vbinrow0, L.vbinoff, L.keys2, L.vals2, p->wbits, L.err, L.rowptr_v, colidx, cval, capacity,
+                        nullptr, nullptr, 1, p->T, 0, 0, 0, &L.vinfo->nbins, p->wbits, (uint32_t)(nwin - 1)};
+            PB_TRY(launch_sort(p, sv, rd.nvbins, st));
+            if (f64) hipLaunchKernelGGL((k_dense<512, double, true>), dim3(dgrid), dim3(512), 0, st, da);
+            else hipLaunchKernelGGL((k_dense<512, float, true>), dim3(dgrid), dim3(512), 0, st, da);
+            PB_LAUNCHED("dense output");
+        }
     }
     return PB_OK;
 }
@@ -319,12 +665,16 @@ pb_status finish_symbolic(pb_plan *p, hipStream_t st) {
     PB_HIP(hipStreamSynchronize(st));
     if (p->h.err) return fail(PB_ERR_INTERNAL, "symbolic device error 0x%x", p->h.err);
     if (p->m == 0) p->h.nbins = 0;
-    if (p->h.noversize)
+    if (p->h.maxrow >= ((uint64_t)1 << 32))
+        return fail(PB_ERR_UNSUPPORTED, "a row of C expands to %llu tuples; at most 2^32 - 1 are supported",
+                    (unsigned long long)p->h.maxrow);
+    if (p->h.noversize && p->count > 1)
         return fail(PB_ERR_UNSUPPORTED,
-                    "%llu rows expand to more than %d tuples (largest %lld); bins larger than the LDS tile are not "
-                    "supported",
+                    "%llu rows expand to more than %d tuples (largest %lld); batched products need every row within "
+                    "the tile",
                     (unsigned long long)p->h.noversize, p->T, (long long)p->h.maxrow);
     p->nchunks = ceil_div((int64_t)p->h.flop, p->chunk);
+    if (p->h.noversize || (p->round_tuples > 0 && (int64_t)p->h.flop > p->round_tuples)) return build_rounds(p, st);
     p->ws_bytes = num_layout(nullptr, p).total;
     return PB_OK;
 }
@@ -342,7 +692,7 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
                            (int64_t)p->chunk, p->k, p->F, L.kstart);
         PB_LAUNCHED("chunk start");
         ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, ari, av, brp, bci, bv, p->runpos, p->rowtab, L.keys, L.vals,
-                      p->cb, L.err};
+                      p->cb, L.err, nullptr, 0};
         ProfScope ps(st, 1);
         const unsigned grid = (unsigned)ceil_div(p->nchunks, 4);
         switch (p->chunk) {
@@ -364,7 +714,7 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
     if (nbins > 0) {
         {
             ProfScope ps(st, 3);
-            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err};
+            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err, p->T, 0, 0, 0, nullptr};
             if (p->T <= kSortTmaxSmall)
                 hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)nbins), dim3(kCountBlock), 0,
                                    st, ca);
@@ -377,7 +727,7 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
                                              SegRowPtrDst{{}, L.outs, p->prob_row0, p->count}, L.status, L.ticket, L.err,
                                              st, "row pointer scan"));
             } else {
-                PB_TRY(launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m}, L.status, L.ticket,
+                PB_TRY(launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m, nullptr}, L.status, L.ticket,
                                           L.err, st, "row pointer scan"));
             }
         }
@@ -393,7 +743,14 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
                     batch ? 0 : C->capacity,
                     batch ? L.outs : nullptr,
                     batch ? p->prob_row0 : nullptr,
-                    p->count};
+                    p->count,
+                    p->T,
+                    0,
+                    0,
+                    0,
+                    nullptr,
+                    0,
+                    0};
         ProfScope ps(st, 2);
         if (p->T <= kSortTmaxSmall) {
             if (f64)
@@ -496,6 +853,18 @@ pb_status launch_pack(pb_plan *p, int what, hipStream_t st) {
 
 }  // namespace
 
+// Status of a finished numeric step from its device error word.
+pb_status numeric_status(uint32_t err, int64_t total, int64_t capacity) {
+    if (err & kErrWide)
+        return fail(PB_ERR_UNSUPPORTED,
+                    "a column window of a wide row exceeds the tile and is wider than the dense accumulator "
+                    "(n above 2^22 with a heavily clustered row)");
+    if (err & ~(uint32_t)kErrCapacity) return fail(PB_ERR_INTERNAL, "numeric device error 0x%x", err);
+    if ((err & kErrCapacity) || total > capacity)
+        return fail(PB_ERR_CAPACITY, "C needs %lld entries, capacity %lld", (long long)total, (long long)capacity);
+    return PB_OK;
+}
+
 extern "C" {
 
 const char *spgemm_status_string(pb_status s) {
@@ -526,7 +895,8 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
     int T, chunk;
-    PB_TRY(resolve_tune(tune, &T, &chunk));
+    int64_t round_tuples;
+    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
     const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1).total;
     if (!sym_ws) {
@@ -552,6 +922,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->T = T;
     p->chunk = chunk;
     p->cb = cb;
+    p->round_tuples = round_tuples;
     p->info = L.info;
     p->F = L.F;
     p->R = L.R;
@@ -592,9 +963,34 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
         return fail(PB_ERR_WORKSPACE, "numeric workspace has %zu bytes, needs %zu", workspace_bytes, p->ws_bytes);
 
     hipStream_t st = (hipStream_t)hip_stream;
+    if (p->m == 0) PB_TRY(fill_zero(C->rowptr, sizeof(int64_t), st));
+    if (p->rounds_mode) {
+        // the rounds share the workspace; each one's error word is read after
+        // it, so a sync per round happens only when nnzC is requested
+        uint32_t err_all = 0;
+        for (size_t i = 0; i < p->rounds.size(); ++i) {
+            const pb_plan::Round &rd = p->rounds[i];
+            PB_TRY(run_round(p, rd, workspace, A, B, C->rowptr + rd.r0, i ? C->rowptr + rd.r0 : nullptr, C->colidx,
+                             C->val, C->capacity, st));
+            if (nnzC) {
+                uint32_t err = 0;
+                PB_HIP(hipMemcpyAsync(&err, round_layout(workspace, p, rd).err, sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, st));
+                PB_HIP(hipStreamSynchronize(st));
+                err_all |= err;
+            }
+        }
+        if (nnzC) {
+            int64_t total = 0;
+            PB_HIP(hipMemcpyAsync(&total, C->rowptr + p->m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            PB_HIP(hipStreamSynchronize(st));
+            *nnzC = total;
+            return numeric_status(err_all, total, C->capacity);
+        }
+        return PB_OK;
+    }
     NumLayout L = num_layout(workspace, p);
     PB_TRY(fill_zero(workspace, L.zero_bytes, st));
-    if (p->m == 0) PB_TRY(fill_zero(C->rowptr, sizeof(int64_t), st));
     PB_TRY(run_numeric(p, L, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, C, st));
     if (nnzC) {
         int64_t total = 0;
@@ -603,10 +999,63 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
         PB_HIP(hipMemcpyAsync(&err, L.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         PB_HIP(hipStreamSynchronize(st));
         *nnzC = total;
-        if (err & ~(uint32_t)kErrCapacity) return fail(PB_ERR_INTERNAL, "numeric device error 0x%x", err);
-        if ((err & kErrCapacity) || total > C->capacity)
-            return fail(PB_ERR_CAPACITY, "C needs %lld entries, capacity %lld", (long long)total,
-                        (long long)C->capacity);
+        return numeric_status(err, total, C->capacity);
+    }
+    return PB_OK;
+}
+
+pb_status spgemm_plan_rounds(const pb_plan *p, int64_t *nrounds, int64_t *row_begin, int64_t *flop_per_round) {
+    if (!p || !nrounds) return fail(PB_ERR_ARG, "NULL argument");
+    if (p->count != 1) return fail(PB_ERR_ARG, "batch plans have no rounds");
+    if (!p->rounds_mode) {
+        *nrounds = 1;
+        if (row_begin) {
+            row_begin[0] = 0;
+            row_begin[1] = p->m;
+        }
+        if (flop_per_round) flop_per_round[0] = (int64_t)p->h.flop;
+        return PB_OK;
+    }
+    *nrounds = (int64_t)p->rounds.size();
+    for (size_t i = 0; i < p->rounds.size(); ++i) {
+        if (row_begin) row_begin[i] = p->rounds[i].r0;
+        if (flop_per_round) flop_per_round[i] = p->rounds[i].flop;
+    }
+    if (row_begin) row_begin[p->rounds.size()] = p->rounds.empty() ? 0 : p->rounds.back().r1;
+    return PB_OK;
+}
+
+pb_status spgemm_numeric_round(pb_plan *p, const pb_csx *A, const pb_csx *B, int64_t round, void *workspace,
+                               size_t workspace_bytes, pb_csr_out *C, int64_t *nnzC, void *hip_stream) {
+    g_last_error.clear();
+    if (!p) return fail(PB_ERR_ARG, "plan is NULL");
+    if (!p->rounds_mode) {
+        if (round != 0) return fail(PB_ERR_ARG, "round %lld out of range (the plan has one round)", (long long)round);
+        return spgemm_numeric(p, A, B, workspace, workspace_bytes, C, nnzC, hip_stream);
+    }
+    if (round < 0 || round >= (int64_t)p->rounds.size())
+        return fail(PB_ERR_ARG, "round %lld out of range (the plan has %zu)", (long long)round, p->rounds.size());
+    PB_TRY(check_csx(A, "A"));
+    PB_TRY(check_csx(B, "B"));
+    if (A->nrows != p->m || A->ncols != p->k || B->ncols != p->n || A->nnz != p->nnzA || B->nnz != p->nnzB)
+        return fail(PB_ERR_SHAPE, "A/B differ from the matrices given to the symbolic step");
+    if (!C || !C->rowptr) return fail(PB_ERR_ARG, "C or C->rowptr is NULL");
+    if (C->capacity < 0) return fail(PB_ERR_SHAPE, "negative capacity");
+    if (C->capacity > 0 && (!C->colidx || !C->val)) return fail(PB_ERR_ARG, "C->colidx/val is NULL");
+    const pb_plan::Round &rd = p->rounds[(size_t)round];
+    if (rd.ws_bytes > 0 && (!workspace || workspace_bytes < rd.ws_bytes))
+        return fail(PB_ERR_WORKSPACE, "numeric workspace has %zu bytes, needs %zu", workspace_bytes, rd.ws_bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (rd.r1 == rd.r0) PB_TRY(fill_zero(C->rowptr, sizeof(int64_t), st));
+    PB_TRY(run_round(p, rd, workspace, A, B, C->rowptr, nullptr, C->colidx, C->val, C->capacity, st));
+    if (nnzC) {
+        int64_t total = 0;
+        uint32_t err = 0;
+        PB_HIP(hipMemcpyAsync(&total, C->rowptr + (rd.r1 - rd.r0), sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        PB_HIP(hipMemcpyAsync(&err, round_layout(workspace, p, rd).err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        PB_HIP(hipStreamSynchronize(st));
+        *nnzC = total;
+        return numeric_status(err, total, C->capacity);
     }
     return PB_OK;
 }
@@ -619,7 +1068,8 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
     int T, chunk;
-    PB_TRY(resolve_tune(tune, &T, &chunk));
+    int64_t round_tuples;
+    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples));
     std::vector<ProbDesc> hd;
     int64_t m, k, n, nnza, nnzb;
     batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);

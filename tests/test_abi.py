@@ -99,6 +99,16 @@ def test_bad_precision_and_tune(lib):
     t.expand_chunk = 1000
     rc, _ = _symbolic(lib, _fake(10, 5, 3), _fake(5, 7, 3), tune=ctypes.byref(t))
     assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
+    t = B.PbTune()
+    t.round_tuples = -1
+    rc, _ = _symbolic(lib, _fake(10, 5, 3), _fake(5, 7, 3), tune=ctypes.byref(t))
+    assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
+
+
+def test_tune_struct_layout():
+    """pb_tune is 32 bytes with round_tuples at offset 8 (as in the header)."""
+    assert ctypes.sizeof(B.PbTune) == 32
+    assert B.PbTune.round_tuples.offset == 8
 
 
 def test_symbolic_workspace_too_small(lib):
@@ -112,6 +122,15 @@ def test_numeric_null_plan(lib):
     a, b = _fake(10, 5, 3), _fake(5, 7, 3)
     out = B.PbCsrOut(0x1000, 0x2000, 0x3000, 10)
     rc = lib.spgemm_numeric(None, ctypes.byref(a), ctypes.byref(b), None, 0, ctypes.byref(out), None, None)
+    assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
+
+
+def test_rounds_null_plan(lib):
+    n = ctypes.c_int64(0)
+    assert B.STATUS_NAMES[lib.spgemm_plan_rounds(None, ctypes.byref(n), None, None)] == "PB_ERR_ARG"
+    a, b = _fake(10, 5, 3), _fake(5, 7, 3)
+    out = B.PbCsrOut(0x1000, 0x2000, 0x3000, 10)
+    rc = lib.spgemm_numeric_round(None, ctypes.byref(a), ctypes.byref(b), 0, None, 0, ctypes.byref(out), None, None)
     assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
 
 

@@ -133,3 +133,15 @@ def test_graph_capture_replays(pb):
             assert torch.equal(ci[:z], eci), f"replay {rep}: columns"
             assert torch.allclose(cv[:z], ecv, rtol=1e-12, atol=0), f"replay {rep}: values"
     plan.close()
+
+
+def test_batch_with_wide_row_is_rejected(pb):
+    """Batched products need every row of C within the tile."""
+    _say("batch with a row wider than the tile")
+    wide = (random_sparse(50, 300, 0.01, 91, "csc", dense_rows=(3,)), random_sparse(300, 400, 0.05, 92, "csr"))
+    probs = [er_problem(500, 3, 93, 94), wide]
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    with pytest.raises(pb.PbError) as ei:
+        pb.spgemm_batch(pairs, tune={"tile_tuples": 256})
+    assert ei.value.name == "PB_ERR_UNSUPPORTED"
+
