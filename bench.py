@@ -306,6 +306,109 @@ def bench_amg(pb, torch, steps, warmup):
     return res
 
 
+def rmat_rows_sample(a, nheavy=32, nrand=96, seed=11):
+    """The heaviest rows of C = A*A (by row flop) and some random rows."""
+    deg = np.diff(a.ptr)
+    rows_of = np.repeat(np.arange(a.nrows), deg)
+    rowflop = np.bincount(rows_of, weights=deg[a.idx].astype(np.float64), minlength=a.nrows)
+    heavy = np.argsort(rowflop)[-nheavy:]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([heavy, rng.integers(0, a.nrows, nrand)])), rowflop
+
+
+def run_rounds(pb, torch, plan, A, B, ws, out, rb, fl, keep_rows=None):
+    """All rounds of a plan into one reused output buffer; with keep_rows,
+    copy those rows of C to the host as each round finishes."""
+    rp, ci, cv = out
+    kept = {}
+    total = 0
+    for r in range(len(fl)):
+        nnz = pb.spgemm_numeric_round(plan, A, B, r, ws, rp, ci, cv, sync=keep_rows is not None)
+        if keep_rows is not None:
+            total += nnz
+            sel = keep_rows[(keep_rows >= rb[r]) & (keep_rows < rb[r + 1])]
+            if sel.size:
+                h_rp = rp[: rb[r + 1] - rb[r] + 1].cpu().numpy()
+                for row in sel:
+                    s0, s1 = int(h_rp[row - rb[r]]), int(h_rp[row - rb[r] + 1])
+                    kept[int(row)] = (ci[s0:s1].cpu().numpy(), cv[s0:s1].cpu().numpy().astype(np.float64))
+    return kept, total
+
+
+def bench_rmat(pb, torch, steps, warmup, scale=20, edge_factor=16, round_tuples=1 << 32):
+    """R-MAT C = A*A (symmetric A: its CSR arrays are its CSC arrays).  Its
+    tuples and C exceed device memory, so the product runs as row-range
+    rounds, each round's C going to one reused buffer (as a consumer that
+    streams C out would); wide (hub) rows go through the column windows."""
+    import oracle
+    from workloads import rmat_symmetric
+
+    t = time.time()
+    a = rmat_symmetric(scale, edge_factor)
+    ac = a.transpose_view()
+    log(f"generated R-MAT scale {scale} ef {edge_factor}: nnz {a.nnz} in {time.time() - t:.1f}s")
+    rows, rowflop = rmat_rows_sample(a)
+    t = time.perf_counter()
+    ref = oracle.spgemm_rows(ac, a, rows, nthreads=len(os.sched_getaffinity(0)))
+    t_oracle = time.perf_counter() - t
+    A = pb.DeviceCsx.from_host(ac)
+    B = pb.DeviceCsx.from_host(a)
+    res = {"workload": f"R-MAT scale {scale}, edge factor {edge_factor}, (a,b,c,d)=(.57,.19,.19,.05), symmetrized, "
+                       f"values U[0,1), C=A*A", "nnz_a": a.nnz, "round_tuples": round_tuples,
+           "oracle_sample": {"rows": int(rows.size), "flop": int(rowflop[rows].sum()),
+                             "seconds": round(t_oracle, 2),
+                             "GFLOPS": round(2 * float(rowflop[rows].sum()) / t_oracle / 1e9, 3)}}
+    base_sec = None
+    for prec in ("f64", "f32c"):
+        tune = {"round_tuples": round_tuples}
+        nsym = pb.spgemm_symbolic(A, B, prec, tune)
+        sym = torch.empty(nsym, dtype=torch.uint8, device="cuda")
+        plan = pb.spgemm_symbolic(A, B, prec, tune, sym_ws=sym)
+        rb, fl = pb.spgemm_plan_rounds(plan)
+        flop = plan.flop
+        ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+        maxrows = max(rb[i + 1] - rb[i] for i in range(len(fl)))
+        cap = max(fl)
+        out = (torch.empty(maxrows + 1, dtype=torch.int64, device="cuda"),
+               torch.empty(cap, dtype=torch.int32, device="cuda"),
+               torch.empty(cap, dtype=torch.float64 if prec == "f64" else torch.float32, device="cuda"))
+        log(f"rmat {prec}: flop {flop}, {len(fl)} rounds, workspace {plan.workspace_bytes / 1e9:.1f} GB")
+        kept, nnz_c = run_rounds(pb, torch, plan, A, B, ws, out, rb, fl, keep_rows=rows)
+        worst = 0.0
+        structure_ok = True
+        for s_, r in enumerate(rows):
+            want_c = ref["idx"][ref["ptr"][s_]:ref["ptr"][s_ + 1]]
+            want_v = ref["val"][ref["ptr"][s_]:ref["ptr"][s_ + 1]]
+            nrm = ref["absval"][ref["ptr"][s_]:ref["ptr"][s_ + 1]]
+            got_c, got_v = kept[int(r)]
+            if not np.array_equal(got_c, want_c):
+                structure_ok = False
+                continue
+            if got_v.size:
+                worst = max(worst, float(np.max(np.abs(got_v - want_v) / nrm)))
+        plan.close()
+
+        def step():
+            p = pb.spgemm_symbolic(A, B, prec, tune, sym_ws=sym)
+            run_rounds(pb, torch, p, A, B, ws, out, rb, fl)
+            p.close()
+
+        sec, prof = time_steps(torch, pb, step, steps, warmup)
+        res[prec] = {"GFLOPS": round(2.0 * flop / sec / 1e9, 3), "ms_per_product": round(sec * 1e3, 2),
+                     "phases_ms_per_product": {k: round(ms / max(steps, 1), 3) for k, (ms, n) in prof.items()},
+                     "flop": flop, "nnz_c": nnz_c, "rounds": len(fl),
+                     "sampled_rows_structure_exact": structure_ok, "max_err_over_N_sampled_rows": worst}
+        log(f"rmat {prec}: {sec * 1e3:.1f} ms per product, {2.0 * flop / sec / 1e9:.1f} GFLOPS, "
+            f"nnz(C) {nnz_c}, sampled rows exact structure {structure_ok}, max err/N {worst:.2e}")
+        if prec == "f64":
+            base_sec = sec
+        else:
+            res["f32c_speedup_vs_f64"] = round(base_sec / sec, 3)
+        del ws, out, sym
+        torch.cuda.empty_cache()
+    return res
+
+
 def summarize_profiles(src: str, out_dir: str, command: str, pmc_command: str) -> None:
     """Turn rocprofv3 CSV output (kernel trace stats and two counter runs,
     FETCH_SIZE then WRITE_SIZE) into the text summaries under profiles/ and
@@ -385,6 +488,8 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also time FP32c (with its error) and the copy bandwidth")
     ap.add_argument("--batched", action="store_true", help="also run the 512-product batched workload")
     ap.add_argument("--amg", action="store_true", help="also run the AMG Galerkin chain")
+    ap.add_argument("--rmat", action="store_true",
+                    help="also run R-MAT scale 20 C=A*A (row-range rounds, wide rows), FP64 and FP32c")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     ap.add_argument("--profile-command", default="", help="the kernel-trace command, recorded in the summaries")
     ap.add_argument("--pmc-command", default="",
@@ -459,6 +564,8 @@ def main():
         out.setdefault("extras", {})["amg"] = bench_amg(pb, torch, max(3, args.steps // 4), 1)
     if args.batched:
         out.setdefault("extras", {})["batched"] = bench_batched(pb, torch, max(2, args.steps // 10), 1)
+    if args.rmat:
+        out.setdefault("extras", {})["rmat"] = bench_rmat(pb, torch, 2, 1)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
         out["cpu_baseline"] = cpu_baseline(a, b)
