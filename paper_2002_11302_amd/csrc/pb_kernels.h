@@ -627,16 +627,21 @@ template <class VT>
 struct Merge;
 template <>
 struct Merge<double> {
-    // plain left-to-right double sum
+    // plain double sum
     double s;
+    __device__ void zero() { s = 0.0; }
     __device__ void start(double v) { s = v; }
     __device__ void add(double v) { s = s + v; }
     __device__ double result() const { return s; }
 };
 template <>
 struct Merge<float> {
-    // Neumaier's compensated sum in float
+    // Neumaier's compensated sum in float: s + c is the running total
     float s, c;
+    __device__ void zero() {
+        s = 0.0f;
+        c = 0.0f;
+    }
     __device__ void start(float v) {
         s = v;
         c = 0.0f;
@@ -649,6 +654,29 @@ struct Merge<float> {
     }
     __device__ float result() const { return s + c; }
 };
+// Sum of two consecutive pieces of a run: x (earlier) then y (later).
+__device__ __forceinline__ Merge<double> merge_cat(const Merge<double> &x, const Merge<double> &y) {
+    Merge<double> r;
+    r.s = x.s + y.s;
+    return r;
+}
+__device__ __forceinline__ Merge<float> merge_cat(const Merge<float> &x, const Merge<float> &y) {
+    Merge<float> r = x;
+    r.add(y.s);  // compensated add of y's running sum
+    r.c = r.c + y.c;
+    return r;
+}
+__device__ __forceinline__ Merge<double> shfl_up_merge(const Merge<double> &x, int d) {
+    Merge<double> r;
+    r.s = __shfl_up(x.s, (unsigned)d, kWave);
+    return r;
+}
+__device__ __forceinline__ Merge<float> shfl_up_merge(const Merge<float> &x, int d) {
+    Merge<float> r;
+    r.s = __shfl_up(x.s, (unsigned)d, kWave);
+    r.c = __shfl_up(x.c, (unsigned)d, kWave);
+    return r;
+}
 
 constexpr uint32_t kBucketLimit = 40;
 
@@ -673,6 +701,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     __shared__ __align__(16) uint8_t smem[OFF_END];
     __shared__ uint32_t s_wsum[NW];
     __shared__ uint32_t s_red[3 * NW];
+    __shared__ uint64_t s_scan[NW + 1];
 
     uint32_t *keyA = (uint32_t *)(smem + OFF_KA);
     uint16_t *slotA = (uint16_t *)(smem + OFF_SA);
@@ -908,13 +937,14 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         }
         __syncthreads();
     }
-    // park the values by slot, then merge runs of equal keys and write them
+    // park the values by slot, then sum every run of equal keys and write it
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         if (p < N) vl[p] = rv[i];
     }
     __syncthreads();
+    // run heads (first tuple of each key), counted per wave
     uint32_t wrun = 0;
     uint32_t hr[IPT];
 #pragma unroll
@@ -928,28 +958,124 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     }
     if (lane == 0) s_wsum[w] = wrun;
     __syncthreads();
-    uint32_t wbase = 0;
-    for (uint32_t ww = 0; ww < w; ++ww) wbase += s_wsum[ww];
+    uint32_t wbase = 0, heads = 0;
+    for (uint32_t ww = 0; ww < NW; ++ww) {
+        if (ww < w) wbase += s_wsum[ww];
+        heads += s_wsum[ww];
+    }
     VT *cv = (VT *)cvals;
+    if ((uint32_t)N - heads <= (uint32_t)N / 16) {
+        // few repeated keys: each head sums its (short) run itself
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        if (hr[i] != 0xffffffffu) {
-            const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-            const uint32_t key = keyA[p];
-            Merge<VT> mg;
-            mg.start(vl[slotA[p]]);
-            for (int q = p + 1; q < N && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
-            const int64_t out = base + wbase + hr[i];
-            if (out < capacity) {
-                const uint32_t vcol =
-                    a.vshift ? ((((uint32_t)row0 + (key >> cb)) & a.vmask) << a.vshift) : 0u;
-                colidx[out] = (int32_t)(vcol | (key & colmask));
-                cv[out] = mg.result();
+        for (int i = 0; i < IPT; ++i) {
+            if (hr[i] != 0xffffffffu) {
+                const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+                const uint32_t key = keyA[p];
+                Merge<VT> mg;
+                mg.start(vl[slotA[p]]);
+                for (int q = p + 1; q < N && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
+                const int64_t out = base + wbase + hr[i];
+                if (out < capacity) {
+                    const uint32_t vcol =
+                        a.vshift ? ((((uint32_t)row0 + (key >> cb)) & a.vmask) << a.vshift) : 0u;
+                    colidx[out] = (int32_t)(vcol | (key & colmask));
+                    cv[out] = mg.result();
+                } else {
+                    atomic_or_agent(a.err, (uint32_t)kErrCapacity);
+                }
+            }
+        }
+        return;
+    }
+    // Many repeated keys: segmented reduction in sorted order: thread t takes sorted positions
+    // [t*IPT, t*IPT + IPT) and sums them left to right, restarting at every
+    // run head; a segmented scan over the threads carries the sum of a run
+    // that started in an earlier thread; the last tuple of each run writes it.
+    const int p0 = (int)threadIdx.x * IPT;
+    uint32_t ks[IPT];
+    Merge<VT> inc[IPT];
+    uint32_t hmask = 0;
+    Merge<VT> acc;
+    acc.zero();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int p = p0 + j;
+        ks[j] = 0;
+        if (p < N) {
+            ks[j] = keyA[p];
+            const VT v = vl[slotA[p]];
+            if (p == 0 || ks[j] != keyA[p - 1]) {
+                hmask |= 1u << j;
+                acc.start(v);
             } else {
-                atomic_or_agent(a.err, (uint32_t)kErrCapacity);
+                acc.add(v);
+            }
+        }
+        inc[j] = acc;
+    }
+    // exclusive segmented scan of the per-thread (has head, sum) pairs
+    bool cf = hmask != 0;
+    Merge<VT> ca = acc;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const bool uf = __shfl_up((int)cf, (unsigned)d, kWave) != 0;
+        const Merge<VT> ua = shfl_up_merge(ca, d);
+        if ((int)lane >= d) {
+            if (!cf) ca = merge_cat(ua, ca);
+            cf = cf || uf;
+        }
+    }
+    // per-wave totals, then the carry into this thread
+    __shared__ Merge<VT> s_wacc[NW];
+    __shared__ uint32_t s_wflag[NW];
+    if (lane == kWave - 1) {
+        s_wacc[w] = ca;
+        s_wflag[w] = cf;
+    }
+    bool xf = __shfl_up((int)cf, 1u, kWave) != 0;
+    Merge<VT> xa = shfl_up_merge(ca, 1);
+    if (lane == 0) {
+        xf = false;
+        xa.zero();
+    }
+    const uint32_t nh = (uint32_t)__builtin_popcount(hmask);
+    uint64_t htot;
+    const uint64_t hbefore = block_excl_scan<BLOCK, SumOp>(nh, s_scan, htot);  // has barriers
+    bool wf = false;
+    Merge<VT> wa;
+    wa.zero();
+    for (uint32_t ww = 0; ww < w; ++ww) {
+        if (s_wflag[ww]) {
+            wa = s_wacc[ww];
+            wf = true;
+        } else {
+            wa = merge_cat(wa, s_wacc[ww]);
+        }
+    }
+    Merge<VT> carry = xf ? xa : merge_cat(wa, xa);
+    uint32_t seen = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int p = p0 + j;
+        if (p < N) {
+            if (hmask & (1u << j)) ++seen;
+            const bool tail = (p == N - 1) || (keyA[p + 1] != ks[j]);
+            if (tail) {
+                const Merge<VT> tot = seen ? inc[j] : merge_cat(carry, inc[j]);
+                const int64_t out = base + (int64_t)hbefore + seen - 1;
+                if (out < capacity) {
+                    const uint32_t key = ks[j];
+                    const uint32_t vcol =
+                        a.vshift ? ((((uint32_t)row0 + (key >> cb)) & a.vmask) << a.vshift) : 0u;
+                    colidx[out] = (int32_t)(vcol | (key & colmask));
+                    cv[out] = tot.result();
+                } else {
+                    atomic_or_agent(a.err, (uint32_t)kErrCapacity);
+                }
             }
         }
     }
+    (void)wf;
 }
 
 // Streaming copy with 16-byte accesses, one element per thread
