@@ -249,6 +249,20 @@ struct BinDst {
     __device__ void side_commit(uint64_t v) const { atomic_max_agent(&info->maxrow, v); }
 };
 
+// Per A entry e = (r, k): the slot of its run's first tuple in the
+// row-ordered tuple array (row r's first slot + the run offset from the
+// row-flop count) and the row part of its keys (r's index inside its bin,
+// shifted above the column bits).  Done once per plan, so the expand reads
+// both directly instead of going through the row table.
+__global__ __launch_bounds__(256) void k_entry_dest(int64_t nnza, const int32_t *ari, const uint32_t *runpos,
+                                                    const RowTab *rowtab, int cb, int64_t *adest, uint32_t *akey) {
+    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (e >= nnza) return;
+    const RowTab rt = rowtab[ari[e]];
+    adest[e] = rt.base + (int64_t)runpos[e];
+    akey[e] = rt.rl << cb;
+}
+
 // kstart[c] = column holding tuple c*C (c < nchunks); kstart[nchunks] = K-1.
 __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64_t *F, int32_t *kstart) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -266,7 +280,7 @@ __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64
 // row k of B with F[k] <= t < F[k+1], and is the product of the i-th entry
 // of A(:,k) and the j-th entry of B(k,:), (i, j) = divmod(t - F[k], nnz(B(k,:))).
 // The tuples of one A entry e = (r, k) form a run that goes to row r's
-// range of the row-ordered tuple array, at offset runpos[e] (fixed by the
+// range of the row-ordered tuple array, starting at adest[e] (fixed by the
 // symbolic step), so bins are contiguous row ranges and no append needs an
 // atomic.  Consecutive lanes take consecutive tuples, so each run is written
 // by consecutive lanes to consecutive addresses.
@@ -280,8 +294,8 @@ struct ExpandArgs {
     const int64_t *brp;
     const int32_t *bci;
     const double *bv;
-    const uint32_t *runpos;
-    const RowTab *rowtab;
+    const int64_t *adest;   // first slot of each A entry's run
+    const uint32_t *akey;   // row part of each A entry's keys
     uint32_t *keys;
     void *vals;
     int cb;
@@ -345,7 +359,6 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
         constexpr int U = 4;
         for (int64_t tt = t; tt < seg_end; tt += U * kWave) {
             int64_t e[U], q[U], jj[U];
-            int32_t r[U];
             bool on[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -357,26 +370,24 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
                 q[u] = bs + j;
                 jj[u] = j;
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) r[u] = on[u] ? a.ari[e[u]] : 0;
-            uint32_t rp[U], col[U];
+            int64_t dst[U];
+            uint32_t kh[U], col[U];
             double av[U], bvv[U];
-            RowTab rt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
-                    rp[u] = a.runpos[e[u]];
+                    dst[u] = a.adest[e[u]];
+                    kh[u] = a.akey[e[u]];
                     av[u] = a.av[e[u]];
                     col[u] = (uint32_t)a.bci[q[u]];
                     bvv[u] = a.bv[q[u]];
-                    rt[u] = a.rowtab[r[u]];
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
-                    const int64_t slot = rt[u].base - a.slot0 + (int64_t)rp[u] + jj[u];
-                    const uint32_t key = (rt[u].rl << a.cb) | col[u];
+                    const int64_t slot = dst[u] - a.slot0 + jj[u];
+                    const uint32_t key = kh[u] | col[u];
                     if ((uint64_t)slot < (uint64_t)a.flop) {
                         a.keys[slot] = key;
                         vals[slot] = (VT)(av[u] * bvv[u]);
