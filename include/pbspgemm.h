@@ -85,7 +85,7 @@ typedef struct {
 
 /* Tuning knobs; 0 selects the default.
  *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096
- *   expand_chunk  tuples per expand wave: 512, 1024 or 2048
+ *   expand_chunk  tuples per expand wave: 256, 512, 1024 or 2048
  *   round_tuples  upper bound on tuples per round (0 = no bound): the rows of
  *                 C are cut into rounds of consecutive bins so that one
  *                 round's tuples fit the workspace (a single bin larger than

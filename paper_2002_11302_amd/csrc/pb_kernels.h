@@ -249,20 +249,6 @@ struct BinDst {
     __device__ void side_commit(uint64_t v) const { atomic_max_agent(&info->maxrow, v); }
 };
 
-// Per A entry e = (r, k): the slot of its run's first tuple in the
-// row-ordered tuple array (row r's first slot + the run offset from the
-// row-flop count) and the row part of its keys (r's index inside its bin,
-// shifted above the column bits).  Done once per plan, so the expand reads
-// both directly instead of going through the row table.
-__global__ __launch_bounds__(256) void k_entry_dest(int64_t nnza, const int32_t *ari, const uint32_t *runpos,
-                                                    const RowTab *rowtab, int cb, int64_t *adest, uint32_t *akey) {
-    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;
-    if (e >= nnza) return;
-    const RowTab rt = rowtab[ari[e]];
-    adest[e] = rt.base + (int64_t)runpos[e];
-    akey[e] = rt.rl << cb;
-}
-
 // kstart[c] = column holding tuple c*C (c < nchunks); kstart[nchunks] = K-1.
 __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64_t *F, int32_t *kstart) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -280,7 +266,7 @@ __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64
 // row k of B with F[k] <= t < F[k+1], and is the product of the i-th entry
 // of A(:,k) and the j-th entry of B(k,:), (i, j) = divmod(t - F[k], nnz(B(k,:))).
 // The tuples of one A entry e = (r, k) form a run that goes to row r's
-// range of the row-ordered tuple array, starting at adest[e] (fixed by the
+// range of the row-ordered tuple array, at offset runpos[e] (fixed by the
 // symbolic step), so bins are contiguous row ranges and no append needs an
 // atomic.  Consecutive lanes take consecutive tuples, so each run is written
 // by consecutive lanes to consecutive addresses.
@@ -294,8 +280,8 @@ struct ExpandArgs {
     const int64_t *brp;
     const int32_t *bci;
     const double *bv;
-    const int64_t *adest;   // first slot of each A entry's run
-    const uint32_t *akey;   // row part of each A entry's keys
+    const uint32_t *runpos;  // offset of each A entry's run inside its row
+    const RowTab *rowtab;    // per row: first slot and index inside its bin
     uint32_t *keys;
     void *vals;
     int cb;
@@ -334,65 +320,94 @@ __device__ __forceinline__ void divmod_u(int64_t x, int64_t d, int64_t &q, int64
 // touches; the column's facts (F[k], where A(:,k) and B(k,:) start, nnz of
 // B(k,:)) are wave-uniform, and each lane takes one tuple of the current
 // 64-tuple step: (i, j) = divmod(t - F[k], nnz(B(k,:))).
+// The body takes every array as a restrict pointer: the arrays it reads are
+// never written by it, so loads of wave-uniform column facts can go through
+// the scalar cache and loads need not wait for earlier stores.
 template <int W, class VT>
-__global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
+__device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const int32_t *__restrict__ kstart,
+                                            const int64_t *__restrict__ acp, const int64_t *__restrict__ astart,
+                                            const int64_t *__restrict__ brp, const int32_t *__restrict__ ari,
+                                            const uint32_t *__restrict__ runpos,
+                                            const RowTab *__restrict__ rowtab, const double *__restrict__ avv,
+                                            const int32_t *__restrict__ bci, const double *__restrict__ bvals,
+                                            uint32_t *__restrict__ keys, VT *__restrict__ vals,
+                                            uint32_t *__restrict__ err, int cb, int64_t flop, int64_t slot0,
+                                            int64_t nchunks) {
     const uint32_t lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wave >= nchunks) return;
     const int64_t t0 = wave * (int64_t)W;
-    const int64_t t1 = (t0 + W < a.flop) ? t0 + W : a.flop;
-    int64_t k = a.kstart[wave];
+    const int64_t t1 = (t0 + W < flop) ? t0 + W : flop;
+    int64_t k = kstart[wave];
     int64_t t = t0;
-    VT *vals = (VT *)a.vals;
     while (t < t1) {
-        const int64_t Fk1 = a.F[k + 1];
+        const int64_t Fk1 = F[k + 1];
         if (Fk1 <= t) {  // column with no tuples left in this chunk
             ++k;
             continue;
         }
-        const int64_t Fk = a.F[k];
-        const int64_t bs = a.brp[k];
-        const int64_t nb = a.brp[k + 1] - bs;
-        const int64_t as = a.astart ? a.astart[k] : a.acp[k];
+        const int64_t Fk = F[k];
+        const int64_t bs = brp[k];
+        const int64_t nb = brp[k + 1] - bs;
+        const int64_t as = astart ? astart[k] : acp[k];
         const int64_t seg_end = Fk1 < t1 ? Fk1 : t1;
+        // column-local views: lanes index them with 32-bit offsets
+        const int32_t *ark = ari + as;
+        const uint32_t *rpk = runpos + as;
+        const double *avk = avv + as;
+        const int32_t *bck = bci + bs;
+        const double *bvk = bvals + bs;
+        // this lane's first tuple of the segment as (A entry i, B entry j);
+        // later steps advance by (64 div nb, 64 mod nb) with a carry
+        int64_t i0, j0;
+        divmod_u(t - Fk + lane, nb, i0, j0);
+        uint32_t ii = (uint32_t)i0, jj = (uint32_t)j0;
+        const uint32_t nbu = (uint32_t)nb;
+        const uint32_t di = nbu > kWave ? 0u : (uint32_t)kWave / nbu;
+        const uint32_t dj = nbu > kWave ? (uint32_t)kWave : (uint32_t)kWave - di * nbu;
         // four 64-tuple steps per iteration, every load issued before use
         constexpr int U = 4;
         for (int64_t tt = t; tt < seg_end; tt += U * kWave) {
-            int64_t e[U], q[U], jj[U];
+            uint32_t iu[U], ju[U];
             bool on[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t my = tt + u * kWave + lane;
-                on[u] = my < seg_end;
-                int64_t i = 0, j = 0;
-                if (on[u]) divmod_u(my - Fk, nb, i, j);
-                e[u] = as + i;
-                q[u] = bs + j;
-                jj[u] = j;
+                on[u] = tt + u * kWave + lane < seg_end;
+                iu[u] = ii;
+                ju[u] = jj;
+                ii += di;
+                jj += dj;
+                if (jj >= nbu) {
+                    jj -= nbu;
+                    ++ii;
+                }
             }
-            int64_t dst[U];
-            uint32_t kh[U], col[U];
+            int32_t r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = on[u] ? ark[iu[u]] : 0;
+            uint32_t rp[U], col[U];
             double av[U], bvv[U];
+            RowTab rt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
-                    dst[u] = a.adest[e[u]];
-                    kh[u] = a.akey[e[u]];
-                    av[u] = a.av[e[u]];
-                    col[u] = (uint32_t)a.bci[q[u]];
-                    bvv[u] = a.bv[q[u]];
+                    rp[u] = rpk[iu[u]];
+                    av[u] = avk[iu[u]];
+                    col[u] = (uint32_t)bck[ju[u]];
+                    bvv[u] = bvk[ju[u]];
+                    rt[u] = rowtab[r[u]];
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
-                    const int64_t slot = dst[u] - a.slot0 + jj[u];
-                    const uint32_t key = kh[u] | col[u];
-                    if ((uint64_t)slot < (uint64_t)a.flop) {
-                        a.keys[slot] = key;
+                    const int64_t slot = rt[u].base - slot0 + (int64_t)rp[u] + ju[u];
+                    const uint32_t key = (rt[u].rl << cb) | col[u];
+                    if ((uint64_t)slot < (uint64_t)flop) {
+                        keys[slot] = key;
                         vals[slot] = (VT)(av[u] * bvv[u]);
                     } else {
-                        atomic_or_agent(a.err, (uint32_t)kErrBinOverflow);
+                        atomic_or_agent(err, (uint32_t)kErrBinOverflow);
                     }
                 }
             }
@@ -400,6 +415,12 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
         t = seg_end;
         ++k;
     }
+}
+
+template <int W, class VT>
+__global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
+    expand_body<W, VT>(a.F, a.kstart, a.acp, a.astart, a.brp, a.ari, a.runpos, a.rowtab, a.av, a.bci, a.bv, a.keys,
+                       (VT *)a.vals, a.err, a.cb, a.flop, a.slot0, nchunks);
 }
 
 // ---------------------------------------------------------------------------

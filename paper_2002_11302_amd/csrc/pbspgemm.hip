@@ -148,8 +148,8 @@ pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tupl
         *T = t->tile_tuples;
     }
     if (t->expand_chunk) {
-        if (t->expand_chunk != 512 && t->expand_chunk != 1024 && t->expand_chunk != 2048)
-            return fail(PB_ERR_ARG, "expand_chunk must be 512, 1024 or 2048");
+        if (t->expand_chunk != 256 && t->expand_chunk != 512 && t->expand_chunk != 1024 && t->expand_chunk != 2048)
+            return fail(PB_ERR_ARG, "expand_chunk must be 256, 512, 1024 or 2048");
         *chunk = t->expand_chunk;
     }
     return PB_OK;
@@ -172,8 +172,6 @@ struct pb_plan {
     uint64_t *R = nullptr;
     RowTab *rowtab = nullptr;
     uint32_t *runpos = nullptr;
-    int64_t *adest = nullptr;
-    uint32_t *akey = nullptr;
     int32_t *binrow0 = nullptr;
     int64_t *binoff = nullptr;
     // batch: packed inputs and problem tables (in the symbolic workspace)
@@ -217,8 +215,6 @@ struct SymLayout {
     int64_t *F;
     RowTab *rowtab;
     uint32_t *runpos;
-    int64_t *adest;
-    uint32_t *akey;
     int32_t *binrow0;
     int64_t *binoff;
     // batch only
@@ -244,8 +240,6 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
     L.F = cv.take<int64_t>(k + 1);
     L.rowtab = cv.take<RowTab>(m);
     L.runpos = cv.take<uint32_t>(nnza);
-    L.adest = cv.take<int64_t>(nnza);
-    L.akey = cv.take<uint32_t>(nnza);
     L.binrow0 = cv.take<int32_t>(m + 1);
     L.binoff = cv.take<int64_t>(m + 1);
     if (count > 1) {
@@ -333,11 +327,6 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
             m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count, -1},
             BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2], &L.info->err, st,
             "bin scan"));
-        if (p->nnzA > 0) {
-            hipLaunchKernelGGL(k_entry_dest, dim3((unsigned)ceil_div(p->nnzA, 256)), dim3(256), 0, st, p->nnzA, ari,
-                               L.runpos, L.rowtab, p->cb, L.adest, L.akey);
-            PB_LAUNCHED("entry destinations");
-        }
     }
     return PB_OK;
 }
@@ -574,10 +563,14 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(nchunks + 1, 256)), dim3(256), 0, st, nchunks,
                            (int64_t)p->chunk, K, F, L.kstart);
         PB_LAUNCHED("chunk start");
-        ExpandArgs ea{rd.flop, K, F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, p->adest,
-                      p->akey, L.keys, L.vals, p->cb, L.err, astart, rd.slot0};
+        ExpandArgs ea{rd.flop, K, F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, p->runpos,
+                      p->rowtab, L.keys, L.vals, p->cb, L.err, astart, rd.slot0};
         const unsigned grid = (unsigned)ceil_div(nchunks, 4);
         switch (p->chunk) {
+            case 256:
+                if (f64) hipLaunchKernelGGL((k_expand<256, double>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                else hipLaunchKernelGGL((k_expand<256, float>), dim3(grid), dim3(256), 0, st, ea, nchunks);
+                break;
             case 512:
                 if (f64) hipLaunchKernelGGL((k_expand<512, double>), dim3(grid), dim3(256), 0, st, ea, nchunks);
                 else hipLaunchKernelGGL((k_expand<512, float>), dim3(grid), dim3(256), 0, st, ea, nchunks);
@@ -702,11 +695,15 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
         hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(p->nchunks + 1, 256)), dim3(256), 0, st, p->nchunks,
                            (int64_t)p->chunk, p->k, p->F, L.kstart);
         PB_LAUNCHED("chunk start");
-        ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, ari, av, brp, bci, bv, p->adest, p->akey, L.keys, L.vals,
+        ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, ari, av, brp, bci, bv, p->runpos, p->rowtab, L.keys, L.vals,
                       p->cb, L.err, nullptr, 0};
         ProfScope ps(st, 1);
         const unsigned grid = (unsigned)ceil_div(p->nchunks, 4);
         switch (p->chunk) {
+            case 256:
+                if (f64) hipLaunchKernelGGL((k_expand<256, double>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                else hipLaunchKernelGGL((k_expand<256, float>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
+                break;
             case 512:
                 if (f64) hipLaunchKernelGGL((k_expand<512, double>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
                 else hipLaunchKernelGGL((k_expand<512, float>), dim3(grid), dim3(256), 0, st, ea, p->nchunks);
@@ -939,8 +936,6 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->R = L.R;
     p->rowtab = L.rowtab;
     p->runpos = L.runpos;
-    p->adest = L.adest;
-    p->akey = L.akey;
     p->binrow0 = L.binrow0;
     p->binoff = L.binoff;
     pb_status rs = fill_zero(sym_ws, L.zero_bytes, st);
@@ -1129,8 +1124,6 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     p->R = L.R;
     p->rowtab = L.rowtab;
     p->runpos = L.runpos;
-    p->adest = L.adest;
-    p->akey = L.akey;
     p->binrow0 = L.binrow0;
     p->binoff = L.binoff;
     p->pdesc = L.pdesc;
