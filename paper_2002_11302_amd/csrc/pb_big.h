@@ -101,7 +101,19 @@ __global__ __launch_bounds__(BLOCK) void k_big_hist(BigArgs a) {
     for (int x = threadIdx.x; x < nwin; x += BLOCK) h[x] = 0;
     __syncthreads();
     const uint32_t colmask = a.cb ? ((1u << a.cb) - 1u) : 0u;
-    for (int64_t p = s + threadIdx.x; p < e; p += BLOCK) atomicAdd(&h[(a.keys[p] & colmask) >> a.wbits], 1u);
+    // eight loads in flight per thread before their histogram updates
+    constexpr int V = 8;
+    for (int64_t p0 = s; p0 < e; p0 += (int64_t)V * BLOCK) {
+        uint32_t kk[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int64_t p = p0 + v * BLOCK + threadIdx.x;
+            kk[v] = p < e ? a.keys[p] : 0u;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (p0 + v * BLOCK + threadIdx.x < e) atomicAdd(&h[(kk[v] & colmask) >> a.wbits], 1u);
+    }
     __syncthreads();
     uint32_t *ch = a.chist + (int64_t)blockIdx.x * nwin;
     for (int x = threadIdx.x; x < nwin; x += BLOCK) {

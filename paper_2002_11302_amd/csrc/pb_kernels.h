@@ -450,8 +450,9 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     constexpr int LOG_TS = (TS >= 16384) ? 14 : (TS >= 8192) ? 13 : (TS >= 4096) ? 12 : 11;
     static_assert((1 << LOG_TS) == TS, "table size must be a power of two");
     constexpr uint32_t EMPTY = 0xffffffffu;
+    static_assert(TS >= TMAX, "the row counters reuse the table");
     __shared__ uint32_t table[TS];
-    __shared__ uint32_t rowcnt[TMAX];
+    uint32_t *rowcnt = table;  // after the table has been read back
     __shared__ uint32_t s_special;
     if (a.nbins) {
         const uint64_t nb = *a.nbins;
@@ -470,7 +471,6 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
         return;
     }
     for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
-    for (int x = threadIdx.x; x < nrows; x += BLOCK) rowcnt[x] = 0;
     if (threadIdx.x == 0) s_special = 0;
     __syncthreads();
     const uint32_t *gk = a.keys + toff;
@@ -502,11 +502,18 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     }
     __syncthreads();
     // Slots hold the bin's distinct keys in hash order, so neighbouring
-    // lanes mostly hit different rows' counters.
-    for (int x = threadIdx.x; x < TS; x += BLOCK) {
-        const uint32_t key = table[x];
-        if (key != EMPTY) atomicAdd(&rowcnt[cb < 32 ? (key >> cb) : 0u], 1u);
-    }
+    // lanes mostly hit different rows' counters.  The slots are read into
+    // registers first; the row counters then take the table's place.
+    constexpr int SPT = TS / BLOCK;
+    uint32_t slot_key[SPT];
+#pragma unroll
+    for (int x = 0; x < SPT; ++x) slot_key[x] = table[x * BLOCK + threadIdx.x];
+    __syncthreads();
+    for (int x = threadIdx.x; x < nrows; x += BLOCK) rowcnt[x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < SPT; ++x)
+        if (slot_key[x] != EMPTY) atomicAdd(&rowcnt[cb < 32 ? (slot_key[x] >> cb) : 0u], 1u);
     __syncthreads();
     if (threadIdx.x == 0 && s_special) rowcnt[cb < 32 ? (EMPTY >> cb) : 0u] += 1;
     __syncthreads();
