@@ -365,6 +365,11 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
         const uint32_t nbu = (uint32_t)nb;
         const uint32_t di = nbu > kWave ? 0u : (uint32_t)kWave / nbu;
         const uint32_t dj = nbu > kWave ? (uint32_t)kWave : (uint32_t)kWave - di * nbu;
+        // the segment's last tuple: lanes past the end load its operands, so
+        // every load is unconditional and the loads of all steps can be in
+        // flight together (only the stores are guarded)
+        int64_t il, jl;
+        divmod_u(seg_end - 1 - Fk, nb, il, jl);
         // four 64-tuple steps per iteration, every load issued before use
         constexpr int U = 4;
         for (int64_t tt = t; tt < seg_end; tt += U * kWave) {
@@ -373,8 +378,8 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 on[u] = tt + u * kWave + lane < seg_end;
-                iu[u] = ii;
-                ju[u] = jj;
+                iu[u] = on[u] ? ii : (uint32_t)il;
+                ju[u] = on[u] ? jj : (uint32_t)jl;
                 ii += di;
                 jj += dj;
                 if (jj >= nbu) {
@@ -384,19 +389,17 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
             }
             int32_t r[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) r[u] = on[u] ? ark[iu[u]] : 0;
+            for (int u = 0; u < U; ++u) r[u] = ark[iu[u]];
             uint32_t rp[U], col[U];
             double av[U], bvv[U];
             RowTab rt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (on[u]) {
-                    rp[u] = rpk[iu[u]];
-                    av[u] = avk[iu[u]];
-                    col[u] = (uint32_t)bck[ju[u]];
-                    bvv[u] = bvk[ju[u]];
-                    rt[u] = rowtab[r[u]];
-                }
+                rp[u] = rpk[iu[u]];
+                av[u] = avk[iu[u]];
+                col[u] = (uint32_t)bck[ju[u]];
+                bvv[u] = bvk[ju[u]];
+                rt[u] = rowtab[r[u]];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
