@@ -86,15 +86,22 @@ typedef struct {
 /* Tuning knobs; 0 selects the default.
  *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096
  *   expand_chunk  tuples per expand wave: 256, 512, 1024 or 2048
- *   round_tuples  upper bound on tuples per round (0 = no bound): the rows of
- *                 C are cut into rounds of consecutive bins so that one
- *                 round's tuples fit the workspace (a single bin larger than
- *                 the bound is a round by itself) */
+ *   round_tuples  upper bound on tuple slots per round (0 = no bound): the
+ *                 rows of C are cut into rounds of consecutive bins so that
+ *                 one round's tuples fit the workspace (a single bin larger
+ *                 than the bound is a round by itself)
+ *   run_align     slots per run are rounded up to a multiple of this (1, 4
+ *                 or 8; 0 = 4 for PB_F64 when nnz(B) >= 12 * B.nrows, else 1).  The
+ *                 tuples of one A entry (a run) then start on a 32-byte
+ *                 sector of the tuple arrays, so runs written by different
+ *                 waves never share a sector; padding slots carry a sentinel
+ *                 key.  Batched plans always use 1. */
 typedef struct {
     int32_t tile_tuples;
     int32_t expand_chunk;
     int64_t round_tuples;
-    int32_t reserved[4];
+    int32_t run_align;
+    int32_t reserved[3];
 } pb_tune;
 
 /* Plan facts (host copy, filled by the symbolic step). */
@@ -108,6 +115,9 @@ typedef struct {
     int32_t col_bits;         /* bits of the column part of a packed key */
     int32_t precision;        /* pb_precision */
     int64_t count;            /* problems in the plan (1 unless batched) */
+    int64_t slots;            /* tuple slots (flop plus run padding) */
+    int32_t run_align;        /* run alignment in slots */
+    int32_t reserved;
 } pb_plan_info;
 
 typedef struct pb_plan pb_plan; /* opaque, host-side */

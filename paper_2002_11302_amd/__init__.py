@@ -125,6 +125,7 @@ def _tune(tune):
     t.tile_tuples = int(tune.get("tile_tuples", 0))
     t.expand_chunk = int(tune.get("expand_chunk", 0))
     t.round_tuples = int(tune.get("round_tuples", 0))
+    t.run_align = int(tune.get("run_align", 0))
     return ctypes.byref(t)
 
 

@@ -43,7 +43,7 @@ class PbCsrOut(ctypes.Structure):
 
 class PbTune(ctypes.Structure):
     _fields_ = [("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("round_tuples", ctypes.c_int64),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("run_align", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class PbPlanInfo(ctypes.Structure):
@@ -51,7 +51,8 @@ class PbPlanInfo(ctypes.Structure):
         ("m", ctypes.c_int64), ("k", ctypes.c_int64), ("n", ctypes.c_int64), ("flop", ctypes.c_int64),
         ("nbins", ctypes.c_int64), ("max_bin_tuples", ctypes.c_int64), ("max_row_flop", ctypes.c_int64),
         ("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("col_bits", ctypes.c_int32),
-        ("precision", ctypes.c_int32), ("count", ctypes.c_int64),
+        ("precision", ctypes.c_int32), ("count", ctypes.c_int64), ("slots", ctypes.c_int64),
+        ("run_align", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

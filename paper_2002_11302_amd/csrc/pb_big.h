@@ -38,10 +38,10 @@ __device__ __forceinline__ int64_t lower_bound_i32(const int32_t *a, int64_t lo,
 }
 
 // astart[k] = first entry of A(:,k) with row >= r0; colflop[k] = entries of
-// A(:,k) with row in [r0, r1) times nnz(B(k,:)).
+// A(:,k) with row in [r0, r1) times the slots of a run of B(k,:).
 __global__ __launch_bounds__(256) void k_round_cols(int64_t K, const int64_t *acp, const int32_t *ari,
-                                                    const int64_t *brp, int32_t r0, int32_t r1, int64_t *astart,
-                                                    uint64_t *colflop) {
+                                                    const int64_t *brp, int32_t r0, int32_t r1, int align,
+                                                    int64_t *astart, uint64_t *colflop) {
     const int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x;
     if (k >= K) return;
     const int64_t a0 = acp[k], a1 = acp[k + 1];
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_round_cols(int64_t K, const int64_t *ac
         e = lower_bound_i32(ari, s, a1, r1);
     }
     astart[k] = s;
-    colflop[k] = (uint64_t)(e - s) * (uint64_t)nb;
+    colflop[k] = (uint64_t)(e - s) * (uint64_t)run_slots(nb, align);
 }
 
 struct U64Src {
@@ -108,11 +108,11 @@ __global__ __launch_bounds__(BLOCK) void k_big_hist(BigArgs a) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int64_t p = p0 + v * BLOCK + threadIdx.x;
-            kk[v] = p < e ? a.keys[p] : 0u;
+            kk[v] = p < e ? a.keys[p] : kSentinel;
         }
 #pragma unroll
         for (int v = 0; v < V; ++v)
-            if (p0 + v * BLOCK + threadIdx.x < e) atomicAdd(&h[(kk[v] & colmask) >> a.wbits], 1u);
+            if (kk[v] != kSentinel) atomicAdd(&h[(kk[v] & colmask) >> a.wbits], 1u);
     }
     __syncthreads();
     uint32_t *ch = a.chist + (int64_t)blockIdx.x * nwin;
@@ -164,21 +164,23 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
         for (int x = threadIdx.x; x < nwin; x += BLOCK) hsc[x] = 0;
         __syncthreads();
         uint32_t col[PER], rank[PER];
+        bool real[PER];
         VT val[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int q = u * BLOCK + threadIdx.x;
             col[u] = 0;
+            real[u] = false;
             if (q < nsub) {
-                col[u] = a.keys[s0 + q] & colmask;
+                const uint32_t key = a.keys[s0 + q];
+                real[u] = key != kSentinel;  // padding slots are dropped here
+                col[u] = key & colmask;
                 val[u] = gv[s0 + q];
             }
         }
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int q = u * BLOCK + threadIdx.x;
-            if (q < nsub) rank[u] = atomicAdd(&hsc[col[u] >> a.wbits], 1u);
-        }
+        for (int u = 0; u < PER; ++u)
+            if (real[u]) rank[u] = atomicAdd(&hsc[col[u] >> a.wbits], 1u);
         __syncthreads();
         // exclusive scan of the step's window counts
         uint32_t cnt[WPT];
@@ -191,6 +193,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
         }
         uint64_t total;
         uint64_t ex = block_excl_scan<BLOCK, SumOp>(tsum, s_scan, total);
+        const int nput = (int)total;  // real tuples of the step
 #pragma unroll
         for (int x = 0; x < WPT; ++x) {
             const int wdx = threadIdx.x * WPT + x;
@@ -200,8 +203,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int q = u * BLOCK + threadIdx.x;
-            if (q < nsub) {
+            if (real[u]) {
                 const uint32_t w = col[u] >> a.wbits;
                 const uint32_t pos = hoff[w] + rank[u];
                 skey[pos] = rlw[w] | (col[u] & wmask);
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < nsub; q += BLOCK) {
+        for (int q = threadIdx.x; q < nput; q += BLOCK) {
             const uint32_t w = swin[q];
             const int64_t dest = cbase[w] + run[w] + (q - (int)hoff[w]);
             if ((uint64_t)dest < (uint64_t)a.nbigflop) {

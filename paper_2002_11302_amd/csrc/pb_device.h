@@ -21,6 +21,10 @@ enum : uint32_t {
 // at ~64 cycles per poll this is well under a second.
 constexpr uint32_t kSpinCap = 1u << 24;
 
+// Key of a padding slot (no tuple).  No real key reaches it: the bin cut
+// keeps the row part of every key below its all-ones value.
+constexpr uint32_t kSentinel = 0xffffffffu;
+
 __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }

@@ -9,6 +9,7 @@ namespace pb {
 // Facts the symbolic step leaves on the device (read back once).
 struct SymInfo {
     uint64_t flop;       // Algorithm 3's multiplication count
+    uint64_t slots;      // tuple slots: runs rounded up to the run alignment
     uint64_t nbins;      // bins of consecutive rows
     uint64_t maxnormal;  // largest row flop among rows <= tile/2
     uint64_t maxrow;     // largest row flop
@@ -88,11 +89,20 @@ struct NoSide {
     __device__ void side_commit(uint64_t) const {}
 };
 
-// Algorithm 3: flop_k = nnz(A(:,k)) * nnz(B(k,:)); F = exclusive scan.
+// Runs (the tuples of one A entry) occupy a multiple of `align` slots, so
+// that runs written by different waves never share a 32-byte sector of the
+// tuple arrays; the slots past a run's end hold the sentinel key.
+__device__ __forceinline__ int64_t run_slots(int64_t nb, int align) {
+    return (nb + align - 1) / align * align;
+}
+
+// Algorithm 3: flop_k = nnz(A(:,k)) * nnz(B(k,:)); F = exclusive scan of
+// the column's tuple slots, nnz(A(:,k)) * run_slots(nnz(B(k,:))).
 struct ColFlopSrc {
     const int64_t *acp, *brp;
+    int align;
     __device__ uint64_t operator()(int64_t k) const {
-        return (uint64_t)((acp[k + 1] - acp[k]) * (brp[k + 1] - brp[k]));
+        return (uint64_t)((acp[k + 1] - acp[k]) * run_slots(brp[k + 1] - brp[k], align));
     }
 };
 struct ColFlopDst : NoSide {
@@ -102,7 +112,7 @@ struct ColFlopDst : NoSide {
     __device__ void operator()(int64_t k, uint64_t excl, uint64_t) const { F[k] = (int64_t)excl; }
     __device__ void total(uint64_t t) const {
         F[K] = (int64_t)t;
-        info->flop = t;
+        info->slots = t;
     }
 };
 
@@ -114,19 +124,26 @@ struct ColFlopDst : NoSide {
 // taken by the whole wave, lanes striding over the column.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp, const int32_t *ari,
-                                                   const int64_t *brp, uint64_t *rowflop, uint32_t *runpos) {
+                                                   const int64_t *brp, int align, uint64_t *rowflop,
+                                                   uint32_t *runpos, SymInfo *info) {
     const int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    int64_t a0 = 0, na = 0, nb = 0;
+    int64_t a0 = 0, na = 0, nb = 0, pnb = 0;
     if (k < K) {
         a0 = acp[k];
         na = acp[k + 1] - a0;
         nb = brp[k + 1] - brp[k];
         if (nb == 0) na = 0;
+        pnb = run_slots(nb, align);
     }
+    // Algorithm 3's multiplication count, one atomic per wave
+    uint64_t f = (uint64_t)(na * nb);
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) f += __shfl_xor(f, d, kWave);
+    if (lane_id() == 0 && f) atomic_add_agent(&info->flop, f);
     const bool longcol = na > 32;
     if (!longcol) {
         for (int64_t e = a0; e < a0 + na; ++e)
-            runpos[e] = (uint32_t)atomic_add_agent(&rowflop[ari[e]], (uint64_t)nb);
+            runpos[e] = (uint32_t)atomic_add_agent(&rowflop[ari[e]], (uint64_t)pnb);
     }
     uint64_t mask = ballot(longcol);
     const uint32_t lane = lane_id();
@@ -135,7 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
         mask &= mask - 1;
         const int64_t la0 = __shfl(a0, L, kWave);
         const int64_t lna = __shfl(na, L, kWave);
-        const int64_t lnb = __shfl(nb, L, kWave);
+        const int64_t lnb = __shfl(pnb, L, kWave);
         for (int64_t e = la0 + lane; e < la0 + lna; e += kWave)
             runpos[e] = (uint32_t)atomic_add_agent(&rowflop[ari[e]], (uint64_t)lnb);
     }
@@ -288,6 +305,7 @@ struct ExpandArgs {
     uint32_t *err;
     const int64_t *astart;  // rounds: first entry of A(:,k) in the round's rows (null: all of A(:,k))
     int64_t slot0;          // rounds: slot of the round's first tuple
+    int align;              // run alignment in slots
 };
 
 // (q, r) = divmod(x, d) for 0 <= x, 1 <= d; float reciprocal with an exact
@@ -332,7 +350,7 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
                                             const int32_t *__restrict__ bci, const double *__restrict__ bvals,
                                             uint32_t *__restrict__ keys, VT *__restrict__ vals,
                                             uint32_t *__restrict__ err, int cb, int64_t flop, int64_t slot0,
-                                            int64_t nchunks) {
+                                            int align, int64_t nchunks) {
     const uint32_t lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wave >= nchunks) return;
@@ -348,7 +366,9 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
         }
         const int64_t Fk = F[k];
         const int64_t bs = brp[k];
-        const int64_t nb = brp[k + 1] - bs;
+        const int64_t nbt = brp[k + 1] - bs;       // B entries of the run
+        const int64_t nb = run_slots(nbt, align);  // its slots (flop space is in slots)
+        const uint32_t lastb = (uint32_t)nbt - 1u;
         const int64_t as = astart ? astart[k] : acp[k];
         const int64_t seg_end = Fk1 < t1 ? Fk1 : t1;
         // column-local views: lanes index them with 32-bit offsets
@@ -395,20 +415,22 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
             RowTab rt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                const uint32_t jb = ju[u] < lastb ? ju[u] : lastb;  // padding slots read the run's last B entry
                 rp[u] = rpk[iu[u]];
                 av[u] = avk[iu[u]];
-                col[u] = (uint32_t)bck[ju[u]];
-                bvv[u] = bvk[ju[u]];
+                col[u] = (uint32_t)bck[jb];
+                bvv[u] = bvk[jb];
                 rt[u] = rowtab[r[u]];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
                     const int64_t slot = rt[u].base - slot0 + (int64_t)rp[u] + ju[u];
-                    const uint32_t key = (rt[u].rl << cb) | col[u];
+                    const bool real = ju[u] <= lastb;
+                    const uint32_t key = real ? ((rt[u].rl << cb) | col[u]) : kSentinel;
                     if ((uint64_t)slot < (uint64_t)flop) {
                         keys[slot] = key;
-                        vals[slot] = (VT)(av[u] * bvv[u]);
+                        vals[slot] = real ? (VT)(av[u] * bvv[u]) : (VT)0;
                     } else {
                         atomic_or_agent(err, (uint32_t)kErrBinOverflow);
                     }
@@ -423,7 +445,7 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
 template <int W, class VT>
 __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
     expand_body<W, VT>(a.F, a.kstart, a.acp, a.astart, a.brp, a.ari, a.runpos, a.rowtab, a.av, a.bci, a.bv, a.keys,
-                       (VT *)a.vals, a.err, a.cb, a.flop, a.slot0, nchunks);
+                       (VT *)a.vals, a.err, a.cb, a.flop, a.slot0, a.align, nchunks);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,7 +478,6 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     static_assert(TS >= TMAX, "the row counters reuse the table");
     __shared__ uint32_t table[TS];
     uint32_t *rowcnt = table;  // after the table has been read back
-    __shared__ uint32_t s_special;
     if (a.nbins) {
         const uint64_t nb = *a.nbins;
         if (blockIdx.x == 0 && threadIdx.x == 0 && nb > gridDim.x) atomic_or_agent(a.err, (uint32_t)kErrGrid);
@@ -474,7 +495,6 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
         return;
     }
     for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
-    if (threadIdx.x == 0) s_special = 0;
     __syncthreads();
     const uint32_t *gk = a.keys + toff;
     const int cb = a.cb;
@@ -490,16 +510,12 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     for (int i = 0; i < IPT; ++i) {
         const uint32_t key = kr[i];
         const int p = i * BLOCK + threadIdx.x;
-        if (p < N) {
-            if (key == EMPTY) {  // the one key equal to the empty marker
-                s_special = 1;
-            } else {
-                uint32_t h = (key * 0x9E3779B1u) >> (32 - LOG_TS);
-                while (true) {
-                    const uint32_t old = atomicCAS(&table[h], EMPTY, key);
-                    if (old == EMPTY || old == key) break;
-                    h = (h + 1) & (TS - 1);
-                }
+        if (p < N && key != kSentinel) {  // padding slots hold the sentinel (== EMPTY)
+            uint32_t h = (key * 0x9E3779B1u) >> (32 - LOG_TS);
+            while (true) {
+                const uint32_t old = atomicCAS(&table[h], EMPTY, key);
+                if (old == EMPTY || old == key) break;
+                h = (h + 1) & (TS - 1);
             }
         }
     }
@@ -518,8 +534,7 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     for (int x = 0; x < SPT; ++x)
         if (slot_key[x] != EMPTY) atomicAdd(&rowcnt[cb < 32 ? (slot_key[x] >> cb) : 0u], 1u);
     __syncthreads();
-    if (threadIdx.x == 0 && s_special) rowcnt[cb < 32 ? (EMPTY >> cb) : 0u] += 1;
-    __syncthreads();
+
     for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 - a.row_base + x] = rowcnt[x];
 }
 
@@ -742,7 +757,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     static_assert(NB % BLOCK == 0, "bucket scan: whole buckets per thread");
     __shared__ __align__(16) uint8_t smem[OFF_END];
     __shared__ uint32_t s_wsum[NW];
-    __shared__ uint32_t s_red[3 * NW];
+    __shared__ uint32_t s_red[4 * NW];
     __shared__ uint64_t s_scan[NW + 1];
 
     uint32_t *keyA = (uint32_t *)(smem + OFF_KA);
@@ -785,18 +800,25 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     }
     const uint32_t *gk = a.keys + toff;
     const VT *gvb = (const VT *)a.vals + toff;
+    // padding slots (sentinel keys) are left out of the sort; they are
+    // counted so that the sorted tuples occupy [0, Nr)
     uint32_t rk[IPT];
     VT rv[IPT];
-    uint32_t kmin = 0xffffffffu, kmax = 0;
+    uint32_t kmin = 0xffffffffu, kmax = 0, nreal = 0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+        rk[i] = kSentinel;
         if (p < N) {
             rk[i] = gk[p];
             rv[i] = gvb[p];
+        }
+        const bool real = rk[i] != kSentinel;
+        if (real) {
             kmin = rk[i] < kmin ? rk[i] : kmin;
             kmax = rk[i] > kmax ? rk[i] : kmax;
         }
+        nreal += popc64(ballot(real));
     }
     for (int x = threadIdx.x; x < NB; x += BLOCK) hist[x] = 0;
 #pragma unroll
@@ -809,21 +831,25 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     if (lane == 0) {
         s_red[w] = kmin;
         s_red[NW + w] = kmax;
+        s_red[3 * NW + w] = nreal;
     }
     __syncthreads();
     kmin = 0xffffffffu;
     kmax = 0;
+    int Nr = 0;
     for (int ww = 0; ww < NW; ++ww) {
         kmin = s_red[ww] < kmin ? s_red[ww] : kmin;
         kmax = s_red[NW + ww] > kmax ? s_red[NW + ww] : kmax;
+        Nr += (int)s_red[3 * NW + ww];
     }
+    if (Nr == 0) return;  // block-uniform: only padding slots
     const uint32_t span = kmax - kmin;
     const int spanbits = span ? 32 - __clz(span) : 0;
     const int sh = spanbits > LOG_NB ? spanbits - LOG_NB : 0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-        if (p < N) atomicAdd(&hist[(rk[i] - kmin) >> sh], 1u);
+        if (rk[i] != kSentinel) atomicAdd(&hist[(rk[i] - kmin) >> sh], 1u);
     }
     __syncthreads();
     {
@@ -861,7 +887,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-            if (p < N) {
+            if (rk[i] != kSentinel) {
                 const uint32_t pos = atomicAdd(&hist[(rk[i] - kmin) >> sh], 1u);
                 keyB[pos] = rk[i];
                 slotB[pos] = (uint16_t)p;
@@ -871,7 +897,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const int q = (int)w * kWave * IPT + i * kWave + (int)lane;
-            if (q < N) {
+            if (q < Nr) {
                 const uint32_t key = keyB[q];
                 const uint32_t bk = (key - kmin) >> sh;
                 const uint32_t be = hist[bk];
@@ -888,7 +914,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         __syncthreads();
     } else {
         // stable LSD radix sort, per-wave ballot ranking
-        const int rowbits = nrows > 1 ? 32 - __clz((uint32_t)(nrows - 1)) : 0;
+        // row bits cover nrows itself, so a padding slot's sentinel (all ones
+        // in the sorted bits) orders after every real key
+        const int rowbits = 32 - __clz((uint32_t)nrows);
         const int bits = rowbits + cb;
         const int passes = (bits + 7) / 8;
         const int dw = passes ? (bits + passes - 1) / passes : 0;
@@ -993,7 +1021,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         bool head = false;
-        if (p < N) head = (p == 0) || (keyA[p] != keyA[p - 1]);
+        if (p < Nr) head = (p == 0) || (keyA[p] != keyA[p - 1]);
         const uint64_t hm = ballot(head);
         hr[i] = head ? (wrun + popc_lt(hm)) : 0xffffffffu;
         wrun += popc64(hm);
@@ -1006,7 +1034,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         heads += s_wsum[ww];
     }
     VT *cv = (VT *)cvals;
-    if ((uint32_t)N - heads <= (uint32_t)N / 16) {
+    if ((uint32_t)Nr - heads <= (uint32_t)Nr / 16) {
         // few repeated keys: each head sums its (short) run itself
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
@@ -1015,7 +1043,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
                 const uint32_t key = keyA[p];
                 Merge<VT> mg;
                 mg.start(vl[slotA[p]]);
-                for (int q = p + 1; q < N && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
+                for (int q = p + 1; q < Nr && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
                 const int64_t out = base + wbase + hr[i];
                 if (out < capacity) {
                     const uint32_t vcol =
@@ -1043,7 +1071,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     for (int j = 0; j < IPT; ++j) {
         const int p = p0 + j;
         ks[j] = 0;
-        if (p < N) {
+        if (p < Nr) {
             ks[j] = keyA[p];
             const VT v = vl[slotA[p]];
             if (p == 0 || ks[j] != keyA[p - 1]) {
@@ -1099,9 +1127,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int p = p0 + j;
-        if (p < N) {
+        if (p < Nr) {
             if (hmask & (1u << j)) ++seen;
-            const bool tail = (p == N - 1) || (keyA[p + 1] != ks[j]);
+            const bool tail = (p == Nr - 1) || (keyA[p + 1] != ks[j]);
             if (tail) {
                 const Merge<VT> tot = seen ? inc[j] : merge_cat(carry, inc[j]);
                 const int64_t out = base + (int64_t)hbefore + seen - 1;

@@ -135,11 +135,15 @@ int col_bits(int64_t n) {
     return 64 - __builtin_clzll((uint64_t)(n - 1));
 }
 
-pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tuples) {
+pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tuples, int *align) {
     *T = kDefaultTile;
     *chunk = kDefaultChunk;
     *round_tuples = 0;
+    *align = 0;
     if (!t) return PB_OK;
+    if (t->run_align != 0 && t->run_align != 1 && t->run_align != 4 && t->run_align != 8)
+        return fail(PB_ERR_ARG, "run_align must be 0 (auto), 1, 4 or 8");
+    *align = t->run_align;
     if (t->round_tuples < 0) return fail(PB_ERR_ARG, "round_tuples must be >= 0");
     *round_tuples = t->round_tuples;
     if (t->tile_tuples) {
@@ -166,6 +170,7 @@ struct pb_plan {
     int32_t user_count = 1;
     pb_precision prec = PB_F64;
     int T = kDefaultTile, chunk = kDefaultChunk, cb = 0;
+    int align = 1;  // run alignment in tuple slots
     // symbolic workspace tables
     SymInfo *info = nullptr;
     int64_t *F = nullptr;
@@ -277,7 +282,7 @@ NumLayout num_layout(void *base, const pb_plan *p) {
     L.kstart = cv.take<int32_t>(p->nchunks + 1);
     L.rownnz = cv.take<uint32_t>(p->m);
     L.outs = p->count > 1 ? cv.take<OutDesc>(p->count) : nullptr;
-    const int64_t flop = (int64_t)p->h.flop;
+    const int64_t flop = (int64_t)p->h.slots;
     L.keys = cv.take<uint32_t>(flop);
     if (p->prec == PB_F64) L.vals = cv.take<double>(flop);
     else L.vals = cv.take<float>(flop);
@@ -312,10 +317,10 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
                        hipStream_t st) {
     const int64_t m = p->m, k = p->k;
     if (k > 0) {
-        PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp}, ColFlopDst{{}, L.F, k, L.info}, L.stF, &L.tickets[0],
-                                  &L.info->err, st, "flop scan"));
-        hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp, L.R,
-                           L.runpos);
+        PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp, p->align}, ColFlopDst{{}, L.F, k, L.info}, L.stF,
+                                  &L.tickets[0], &L.info->err, st, "flop scan"));
+        hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp,
+                           p->align, L.R, L.runpos, L.info);
         PB_LAUNCHED("rowflop");
     } else {
         PB_TRY(fill_zero(L.F, sizeof(int64_t), st));
@@ -553,7 +558,7 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         ProfScope ps(st, 1);
         if (partial) {
             hipLaunchKernelGGL(k_round_cols, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, st, K, A->ptr, A->idx,
-                               B->ptr, (int32_t)rd.r0, (int32_t)rd.r1, L.astart, L.colflop);
+                               B->ptr, (int32_t)rd.r0, (int32_t)rd.r1, p->align, L.astart, L.colflop);
             PB_LAUNCHED("round columns");
             PB_TRY(launch_scan<SumOp>(K, U64Src{L.colflop}, ColFlopDst{{}, L.F, K, L.rinfo}, L.st_cols,
                                       &L.tickets[1], L.err, st, "round flop scan"));
@@ -564,7 +569,7 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
                            (int64_t)p->chunk, K, F, L.kstart);
         PB_LAUNCHED("chunk start");
         ExpandArgs ea{rd.flop, K, F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, p->runpos,
-                      p->rowtab, L.keys, L.vals, p->cb, L.err, astart, rd.slot0};
+                      p->rowtab, L.keys, L.vals, p->cb, L.err, astart, rd.slot0, p->align};
         const unsigned grid = (unsigned)ceil_div(nchunks, 4);
         switch (p->chunk) {
             case 256:
@@ -677,8 +682,8 @@ pb_status finish_symbolic(pb_plan *p, hipStream_t st) {
                     "%llu rows expand to more than %d tuples (largest %lld); batched products need every row within "
                     "the tile",
                     (unsigned long long)p->h.noversize, p->T, (long long)p->h.maxrow);
-    p->nchunks = ceil_div((int64_t)p->h.flop, p->chunk);
-    if (p->h.noversize || (p->round_tuples > 0 && (int64_t)p->h.flop > p->round_tuples)) return build_rounds(p, st);
+    p->nchunks = ceil_div((int64_t)p->h.slots, p->chunk);
+    if (p->h.noversize || (p->round_tuples > 0 && (int64_t)p->h.slots > p->round_tuples)) return build_rounds(p, st);
     p->ws_bytes = num_layout(nullptr, p).total;
     return PB_OK;
 }
@@ -687,7 +692,7 @@ pb_status finish_symbolic(pb_plan *p, hipStream_t st) {
 // For a single product `C` is its output; for a batch L.outs holds them.
 pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const int32_t *ari, const double *av,
                       const int64_t *brp, const int32_t *bci, const double *bv, const pb_csr_out *C, hipStream_t st) {
-    const int64_t flop = (int64_t)p->h.flop;
+    const int64_t flop = (int64_t)p->h.slots;
     const int64_t nbins = (int64_t)p->h.nbins;
     const bool batch = p->count > 1;
     const bool f64 = p->prec == PB_F64;
@@ -696,7 +701,7 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
                            (int64_t)p->chunk, p->k, p->F, L.kstart);
         PB_LAUNCHED("chunk start");
         ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, ari, av, brp, bci, bv, p->runpos, p->rowtab, L.keys, L.vals,
-                      p->cb, L.err, nullptr, 0};
+                      p->cb, L.err, nullptr, 0, p->align};
         ProfScope ps(st, 1);
         const unsigned grid = (unsigned)ceil_div(p->nchunks, 4);
         switch (p->chunk) {
@@ -902,9 +907,9 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
         return fail(PB_ERR_SHAPE, "A.ncols (%lld) != B.nrows (%lld)", (long long)A->ncols, (long long)B->nrows);
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk;
+    int T, chunk, align;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples));
+    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
     const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1).total;
     if (!sym_ws) {
@@ -931,6 +936,12 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->chunk = chunk;
     p->cb = cb;
     p->round_tuples = round_tuples;
+    // FP64 runs padded to 4 slots (whole 32-byte sectors of values) when B's
+    // rows are long enough on average for the padding to cost little next to
+    // the partial-sector writes it avoids (measured: ER 2^20 d=16 step -3%;
+    // 8 slots saves more in the expand but costs more in the sort, and FP32c
+    // gains nothing)
+    p->align = align ? align : (prec == PB_F64 && k > 0 && B->nnz >= 12 * k ? 4 : 1);
     p->info = L.info;
     p->F = L.F;
     p->R = L.R;
@@ -1021,7 +1032,7 @@ pb_status spgemm_plan_rounds(const pb_plan *p, int64_t *nrounds, int64_t *row_be
             row_begin[0] = 0;
             row_begin[1] = p->m;
         }
-        if (flop_per_round) flop_per_round[0] = (int64_t)p->h.flop;
+        if (flop_per_round) flop_per_round[0] = (int64_t)p->h.slots;
         return PB_OK;
     }
     *nrounds = (int64_t)p->rounds.size();
@@ -1075,9 +1086,9 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     PB_TRY(check_batch(count, A, B));
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk;
+    int T, chunk, align;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples));
+    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align));
     std::vector<ProbDesc> hd;
     int64_t m, k, n, nnza, nnzb;
     batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);
@@ -1247,6 +1258,8 @@ pb_status spgemm_plan_info(const pb_plan *p, pb_plan_info *info) {
     info->k = p->k;
     info->n = p->n;
     info->flop = (int64_t)p->h.flop;
+    info->slots = (int64_t)p->h.slots;
+    info->run_align = p->align;
     info->nbins = (int64_t)p->h.nbins;
     info->max_bin_tuples = p->T;
     info->max_row_flop = (int64_t)p->h.maxrow;

@@ -106,9 +106,18 @@ def test_bad_precision_and_tune(lib):
 
 
 def test_tune_struct_layout():
-    """pb_tune is 32 bytes with round_tuples at offset 8 (as in the header)."""
+    """pb_tune is 32 bytes with round_tuples at offset 8 and run_align at 16
+    (as in the header)."""
     assert ctypes.sizeof(B.PbTune) == 32
     assert B.PbTune.round_tuples.offset == 8
+    assert B.PbTune.run_align.offset == 16
+
+
+def test_bad_run_align(lib):
+    t = B.PbTune()
+    t.run_align = 3
+    rc, _ = _symbolic(lib, _fake(10, 5, 3), _fake(5, 7, 3), tune=ctypes.byref(t))
+    assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
 
 
 def test_symbolic_workspace_too_small(lib):

@@ -238,3 +238,28 @@ def test_full_bins_repeated(pb, tile):
     ref = oracle.spgemm(a, b)
     for _ in range(4):
         _compare(_run(pb, a, b, "f64", tune={"tile_tuples": tile}), ref, "f64")
+
+
+@pytest.mark.parametrize("align", [1, 4, 8])
+def test_run_alignment(pb, align):
+    """Runs padded to 1, 4 or 8 slots (padding carries the sentinel key):
+    C is the same; B's rows have uneven lengths, so runs end mid-sector."""
+    import torch
+
+    _say(f"ER 30011 d=16 run_align={align}")
+    a, b = er_problem(30011, 16, 21, 22, values="signed")
+    ref = oracle.spgemm(a, b)
+    A, B = pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)
+    for prec in ("f64", "f32c"):
+        got = pb.spgemm(A, B, precision=prec, tune={"run_align": align}).to_host()
+        _compare(got, ref, prec)
+    nsym = pb.spgemm_symbolic(A, B, "f64", {"run_align": align})
+    plan = pb.spgemm_symbolic(A, B, "f64", {"run_align": align},
+                              sym_ws=torch.empty(nsym, dtype=torch.uint8, device="cuda"))
+    info = plan.info()
+    assert info["run_align"] == align and info["flop"] == ref["flop"]
+    nb = np.diff(b.ptr)
+    na = np.diff(a.ptr)
+    assert info["slots"] == int(np.sum(na * ((nb + align - 1) // align * align)))
+    plan.close()
+

@@ -52,7 +52,7 @@ def test_rmat_scale20_rounds(setup, precision):
     sym = torch.empty(nsym, dtype=torch.uint8, device="cuda")
     plan = pb.spgemm_symbolic(A, B, precision, tune, sym_ws=sym)
     rb, fl = pb.spgemm_plan_rounds(plan)
-    assert rb[0] == 0 and rb[-1] == a.nrows and sum(fl) == plan.flop
+    assert rb[0] == 0 and rb[-1] == a.nrows and sum(fl) == plan.info()["slots"] >= plan.flop
     _say(f"{precision}: flop {plan.flop}, {len(fl)} rounds, workspace {plan.workspace_bytes / 1e9:.1f} GB")
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     maxrows = max(rb[i + 1] - rb[i] for i in range(len(fl)))
