@@ -95,13 +95,22 @@ typedef struct {
  *                 tuples of one A entry (a run) then start on a 32-byte
  *                 sector of the tuple arrays, so runs written by different
  *                 waves never share a sector; padding slots carry a sentinel
- *                 key.  Batched plans always use 1. */
+ *                 key.  Batched plans always use 1.
+ *   row_count     how the symbolic step counts tuples per row of C and
+ *                 places each A entry's run inside its row: 1 = one device
+ *                 atomic per entry of A; 2 = row buckets (the entries of A
+ *                 are first distributed to buckets of 4096 consecutive rows
+ *                 by a counting sort, then each bucket counts in LDS; needs
+ *                 0 < nnz(A) < 2^32 and at most 2^25 rows, else PB_ERR_ARG);
+ *                 0 = 2 when it applies, else 1.  C is the same either way
+ *                 up to the order in which equal positions are summed. */
 typedef struct {
     int32_t tile_tuples;
     int32_t expand_chunk;
     int64_t round_tuples;
     int32_t run_align;
-    int32_t reserved[3];
+    int32_t row_count;
+    int32_t reserved[2];
 } pb_tune;
 
 /* Plan facts (host copy, filled by the symbolic step). */
@@ -117,7 +126,7 @@ typedef struct {
     int64_t count;            /* problems in the plan (1 unless batched) */
     int64_t slots;            /* tuple slots (flop plus run padding) */
     int32_t run_align;        /* run alignment in slots */
-    int32_t reserved;
+    int32_t row_count;        /* 1 device atomics, 2 row buckets (see pb_tune) */
 } pb_plan_info;
 
 typedef struct pb_plan pb_plan; /* opaque, host-side */

@@ -126,6 +126,7 @@ def _tune(tune):
     t.expand_chunk = int(tune.get("expand_chunk", 0))
     t.round_tuples = int(tune.get("round_tuples", 0))
     t.run_align = int(tune.get("run_align", 0))
+    t.row_count = int(tune.get("row_count", 0))
     return ctypes.byref(t)
 
 

@@ -43,7 +43,8 @@ class PbCsrOut(ctypes.Structure):
 
 class PbTune(ctypes.Structure):
     _fields_ = [("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("round_tuples", ctypes.c_int64),
-                ("run_align", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("run_align", ctypes.c_int32), ("row_count", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class PbPlanInfo(ctypes.Structure):
@@ -52,7 +53,7 @@ class PbPlanInfo(ctypes.Structure):
         ("nbins", ctypes.c_int64), ("max_bin_tuples", ctypes.c_int64), ("max_row_flop", ctypes.c_int64),
         ("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("col_bits", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("count", ctypes.c_int64), ("slots", ctypes.c_int64),
-        ("run_align", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("run_align", ctypes.c_int32), ("row_count", ctypes.c_int32),
     ]
 
 

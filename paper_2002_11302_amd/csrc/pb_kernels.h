@@ -158,6 +158,133 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
     }
 }
 
+// ---------------------------------------------------------------------------
+// Per-row flop and run offsets without device atomics (products with fewer
+// than 2^32 entries in A and in B).  The rows are cut into buckets of
+// kRowBucketRows consecutive rows.  A counting sort first distributes the
+// entries of A to their row's bucket (per-workgroup LDS histogram over a
+// contiguous range of columns, a scan of the bucket-major histogram, then a
+// scatter at LDS cursors); one workgroup per bucket then adds each entry's
+// run slots to its row's LDS counter, and the fetched value is the entry's
+// run offset.  Same result as k_rowflop up to the order of the runs in a row.
+constexpr int kRowBucketBits = 12;
+constexpr int kRowBucketRows = 1 << kRowBucketBits;
+constexpr int kMaxRowBuckets = 8192;           // LDS histogram of the distribution
+constexpr uint32_t kRunField = 0xfffffu;       // 20-bit run-slot field; saturated:
+                                               // runpos holds the column instead
+struct RowBucketArgs {
+    int64_t K;
+    const int64_t *acp, *brp;
+    const int32_t *ari;
+    int align;
+    int cpt;         // columns per thread of the distribution passes
+    int nbkt, ngrp;  // buckets; workgroups of the distribution passes
+    uint32_t *hist;  // nbkt x ngrp counts (bucket-major), then their scan
+    uint2 *rec;      // per entry, bucket order: (entry, row in bucket | slots << 12)
+    uint32_t *runpos;
+    uint64_t *rowflop;
+    SymInfo *info;
+};
+
+// Visits every A entry of this workgroup's columns: f(e, row, slots, k).
+// One thread per column; columns longer than 32 entries are taken by the
+// whole wave, lanes striding over the column.  Returns the multiplications
+// of this thread's columns.
+template <int BLOCK, class F>
+__device__ __forceinline__ uint64_t visit_entries(const RowBucketArgs &a, F &&f) {
+    uint64_t flop = 0;
+    const uint32_t lane = lane_id();
+    for (int i = 0; i < a.cpt; ++i) {
+        const int64_t k = ((int64_t)blockIdx.x * a.cpt + i) * BLOCK + threadIdx.x;
+        int64_t a0 = 0, na = 0, nb = 0;
+        if (k < a.K) {
+            a0 = a.acp[k];
+            na = a.acp[k + 1] - a0;
+            nb = a.brp[k + 1] - a.brp[k];
+            if (nb == 0) na = 0;
+        }
+        flop += (uint64_t)(na * nb);
+        const int64_t pnb = run_slots(nb, a.align);
+        const bool longcol = na > 32;
+        if (!longcol)
+            for (int64_t e = a0; e < a0 + na; ++e) f(e, a.ari[e], pnb, k);
+        uint64_t mask = ballot(longcol);
+        while (mask) {
+            const int L = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int64_t la0 = __shfl(a0, L, kWave);
+            const int64_t lna = __shfl(na, L, kWave);
+            const int64_t lnb = __shfl(pnb, L, kWave);
+            const int64_t lk = __shfl(k, L, kWave);
+            for (int64_t e = la0 + lane; e < la0 + lna; e += kWave) f(e, a.ari[e], lnb, lk);
+        }
+    }
+    return flop;
+}
+
+// (dynamic LDS: one counter per bucket)
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_hist(RowBucketArgs a) {
+    extern __shared__ uint32_t s_h[];
+    for (int b = threadIdx.x; b < a.nbkt; b += BLOCK) s_h[b] = 0;
+    __syncthreads();
+    uint64_t f = visit_entries<BLOCK>(a, [&](int64_t, int32_t r, int64_t, int64_t) {
+        atomicAdd(&s_h[r >> kRowBucketBits], 1u);
+    });
+    // Algorithm 3's multiplication count, one atomic per wave
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) f += __shfl_xor(f, d, kWave);
+    if (lane_id() == 0 && f) atomic_add_agent(&a.info->flop, f);
+    __syncthreads();
+    for (int b = threadIdx.x; b < a.nbkt; b += BLOCK) a.hist[(int64_t)b * a.ngrp + blockIdx.x] = s_h[b];
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_scatter(RowBucketArgs a) {
+    extern __shared__ uint32_t s_cur[];
+    for (int b = threadIdx.x; b < a.nbkt; b += BLOCK) s_cur[b] = a.hist[(int64_t)b * a.ngrp + blockIdx.x];
+    __syncthreads();
+    visit_entries<BLOCK>(a, [&](int64_t e, int32_t r, int64_t slots, int64_t k) {
+        const uint32_t pos = atomicAdd(&s_cur[r >> kRowBucketBits], 1u);
+        const uint32_t field = slots < (int64_t)kRunField ? (uint32_t)slots : kRunField;
+        if (field == kRunField) a.runpos[e] = (uint32_t)k;
+        a.rec[pos] = make_uint2((uint32_t)e, (uint32_t)(r & (kRowBucketRows - 1)) | field << kRowBucketBits);
+    });
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t m) {
+    __shared__ unsigned long long s_cnt[kRowBucketRows];
+    for (int i = threadIdx.x; i < kRowBucketRows; i += BLOCK) s_cnt[i] = 0;
+    __syncthreads();
+    const int64_t b = blockIdx.x;
+    const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += BLOCK) {
+        const uint2 r = a.rec[p];
+        uint64_t slots = r.y >> kRowBucketBits;
+        if (slots == kRunField) {
+            const uint32_t k = a.runpos[r.x];
+            slots = (uint64_t)run_slots(a.brp[k + 1] - a.brp[k], a.align);
+        }
+        a.runpos[r.x] = (uint32_t)atomicAdd(&s_cnt[r.y & (kRowBucketRows - 1)], (unsigned long long)slots);
+    }
+    __syncthreads();
+    const int64_t r0 = b << kRowBucketBits;
+    for (int i = threadIdx.x; i < kRowBucketRows && r0 + i < m; i += BLOCK) a.rowflop[r0 + i] = s_cnt[i];
+}
+
+// Exclusive scan of the bucket-major histogram, in place (total at [n]).
+struct HistSrc {
+    const uint32_t *h;
+    __device__ uint64_t operator()(int64_t i) const { return h[i]; }
+};
+struct HistDst : NoSide {
+    uint32_t *h;
+    int64_t n;
+    __device__ void operator()(int64_t i, uint64_t excl, uint64_t) const { h[i] = (uint32_t)excl; }
+    __device__ void total(uint64_t t) const { h[n] = (uint32_t)t; }
+};
+
 // R = exclusive scan of rowflop (in place); side: largest row flop <= T/2.
 struct RowFlopSrc {
     const uint64_t *rf;

@@ -135,12 +135,15 @@ int col_bits(int64_t n) {
     return 64 - __builtin_clzll((uint64_t)(n - 1));
 }
 
-pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tuples, int *align) {
+pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tuples, int *align, int *rowcount) {
     *T = kDefaultTile;
     *chunk = kDefaultChunk;
     *round_tuples = 0;
     *align = 0;
+    *rowcount = 0;
     if (!t) return PB_OK;
+    if (t->row_count < 0 || t->row_count > 2) return fail(PB_ERR_ARG, "row_count must be 0 (auto), 1 or 2");
+    *rowcount = t->row_count;
     if (t->run_align != 0 && t->run_align != 1 && t->run_align != 4 && t->run_align != 8)
         return fail(PB_ERR_ARG, "run_align must be 0 (auto), 1, 4 or 8");
     *align = t->run_align;
@@ -171,6 +174,7 @@ struct pb_plan {
     pb_precision prec = PB_F64;
     int T = kDefaultTile, chunk = kDefaultChunk, cb = 0;
     int align = 1;  // run alignment in tuple slots
+    int rowcount = 1;  // per-row flop: 1 device atomics, 2 row buckets
     // symbolic workspace tables
     SymInfo *info = nullptr;
     int64_t *F = nullptr;
@@ -222,6 +226,11 @@ struct SymLayout {
     uint32_t *runpos;
     int32_t *binrow0;
     int64_t *binoff;
+    // row buckets (rowcount 2)
+    uint64_t *stH;
+    uint32_t *hist;
+    uint2 *rec;
+    int nbkt, ngrp, cpt;
     // batch only
     ProbDesc *pdesc;
     int64_t *prob_row0;
@@ -231,9 +240,38 @@ struct SymLayout {
     size_t zero_bytes, total;
 };
 
-SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnzb, int32_t count) {
+// Shape of the row-bucket distribution: buckets of kRowBucketRows rows;
+// at most 2048 workgroups of 256 threads, each over a contiguous range of
+// columns (cpt columns per thread).
+struct BucketShape {
+    int nbkt, ngrp, cpt;
+    int64_t nhist() const { return (int64_t)nbkt * ngrp; }
+};
+BucketShape bucket_shape(int64_t m, int64_t k) {
+    BucketShape s{};
+    s.nbkt = (int)ceil_div(m, kRowBucketRows);
+    s.cpt = (int)std::max<int64_t>(1, ceil_div(k, (int64_t)256 * 2048));
+    s.ngrp = (int)ceil_div(k, (int64_t)256 * s.cpt);
+    return s;
+}
+
+// Row buckets when A has fewer than 2^32 entries (32-bit positions) and the
+// bucket histogram fits LDS; device atomics otherwise.
+int pick_rowcount(int requested, int64_t m, int64_t k, int64_t nnza) {
+    const bool ok = m > 0 && k > 0 && nnza < ((int64_t)1 << 32) && ceil_div(m, kRowBucketRows) <= kMaxRowBuckets;
+    if (requested == 1) return 1;
+    if (requested == 2) return ok ? 2 : -1;
+    return ok ? 2 : 1;
+}
+
+SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnzb, int32_t count, int rowcount) {
     Carver cv(base);
     SymLayout L{};
+    BucketShape bs{};
+    if (rowcount == 2) bs = bucket_shape(m, k);
+    L.nbkt = bs.nbkt;
+    L.ngrp = bs.ngrp;
+    L.cpt = bs.cpt;
     // zeroed region first
     L.info = cv.take<SymInfo>(1);
     L.tickets = cv.take<uint32_t>(4);
@@ -241,12 +279,17 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
     L.stR = cv.take<uint64_t>(ceil_div(m, kScanTile) + 1);
     L.stB = cv.take<uint64_t>(ceil_div(m, kScanTile) + 1);
     L.R = cv.take<uint64_t>(m + 1);
+    L.stH = rowcount == 2 ? cv.take<uint64_t>(ceil_div(bs.nhist(), kScanTile) + 1) : nullptr;
     L.zero_bytes = cv.mark();
     L.F = cv.take<int64_t>(k + 1);
     L.rowtab = cv.take<RowTab>(m);
     L.runpos = cv.take<uint32_t>(nnza);
     L.binrow0 = cv.take<int32_t>(m + 1);
     L.binoff = cv.take<int64_t>(m + 1);
+    if (rowcount == 2) {
+        L.hist = cv.take<uint32_t>(bs.nhist() + 1);
+        L.rec = cv.take<uint2>(nnza);
+    }
     if (count > 1) {
         L.pdesc = cv.take<ProbDesc>(count);
         L.prob_row0 = cv.take<int64_t>(count);
@@ -319,9 +362,24 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
     if (k > 0) {
         PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp, p->align}, ColFlopDst{{}, L.F, k, L.info}, L.stF,
                                   &L.tickets[0], &L.info->err, st, "flop scan"));
-        hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp,
-                           p->align, L.R, L.runpos, L.info);
-        PB_LAUNCHED("rowflop");
+        if (p->rowcount == 2) {
+            const RowBucketArgs ra{k,      acp,    brp,    ari,   p->align, L.cpt, L.nbkt,
+                                   L.ngrp, L.hist, L.rec, L.runpos, L.R,  L.info};
+            const int64_t nh = (int64_t)L.nbkt * L.ngrp;
+            const size_t lds = (size_t)L.nbkt * sizeof(uint32_t);
+            hipLaunchKernelGGL(k_bucket_hist<256>, dim3((unsigned)L.ngrp), dim3(256), lds, st, ra);
+            PB_LAUNCHED("bucket histogram");
+            PB_TRY(launch_scan<SumOp>(nh, HistSrc{L.hist}, HistDst{{}, L.hist, nh}, L.stH, &L.tickets[3],
+                                      &L.info->err, st, "bucket scan"));
+            hipLaunchKernelGGL(k_bucket_scatter<256>, dim3((unsigned)L.ngrp), dim3(256), lds, st, ra);
+            PB_LAUNCHED("bucket scatter");
+            hipLaunchKernelGGL(k_bucket_count<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
+            PB_LAUNCHED("bucket count");
+        } else {
+            hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp,
+                               p->align, L.R, L.runpos, L.info);
+            PB_LAUNCHED("rowflop");
+        }
     } else {
         PB_TRY(fill_zero(L.F, sizeof(int64_t), st));
     }
@@ -907,11 +965,14 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
         return fail(PB_ERR_SHAPE, "A.ncols (%lld) != B.nrows (%lld)", (long long)A->ncols, (long long)B->nrows);
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk, align;
+    int T, chunk, align, rowreq;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align));
+    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align, &rowreq));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
-    const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1).total;
+    const int rowcount = pick_rowcount(rowreq, m, k, A->nnz);
+    if (rowcount < 0)
+        return fail(PB_ERR_ARG, "row_count 2 needs 0 < nnz(A) < 2^32 and at most %d rows", kMaxRowBuckets * kRowBucketRows);
+    const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1, rowcount).total;
     if (!sym_ws) {
         *sym_ws_bytes = need;
         return PB_OK;
@@ -924,8 +985,9 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     if (cb > 31) return fail(PB_ERR_RANGE, "n too large for packed keys");
 
     hipStream_t st = (hipStream_t)hip_stream;
-    SymLayout L = sym_layout(sym_ws, m, k, A->nnz, B->nnz, 1);
+    SymLayout L = sym_layout(sym_ws, m, k, A->nnz, B->nnz, 1, rowcount);
     pb_plan *p = new pb_plan();
+    p->rowcount = rowcount;
     p->m = m;
     p->k = k;
     p->n = n;
@@ -1086,9 +1148,9 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     PB_TRY(check_batch(count, A, B));
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk, align;
+    int T, chunk, align, rowreq;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align));
+    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align, &rowreq));
     std::vector<ProbDesc> hd;
     int64_t m, k, n, nnza, nnzb;
     batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);
@@ -1096,7 +1158,10 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     // the device tables always hold at least two problems (a batch of one
     // gets an empty second problem) so that the batch code paths apply
     const int32_t cnt = count > 1 ? count : 2;
-    const size_t need = sym_layout(nullptr, m, k, nnza, nnzb, cnt).total;
+    const int rowcount = pick_rowcount(rowreq, m, k, nnza);
+    if (rowcount < 0)
+        return fail(PB_ERR_ARG, "row_count 2 needs 0 < nnz(A) < 2^32 and at most %d rows", kMaxRowBuckets * kRowBucketRows);
+    const size_t need = sym_layout(nullptr, m, k, nnza, nnzb, cnt, rowcount).total;
     if (!sym_ws) {
         *sym_ws_bytes = need;
         return PB_OK;
@@ -1117,8 +1182,9 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     }
 
     hipStream_t st = (hipStream_t)hip_stream;
-    SymLayout L = sym_layout(sym_ws, m, k, nnza, nnzb, cnt);
+    SymLayout L = sym_layout(sym_ws, m, k, nnza, nnzb, cnt, rowcount);
     pb_plan *p = new pb_plan();
+    p->rowcount = rowcount;
     p->m = m;
     p->k = k;
     p->n = n;
@@ -1260,6 +1326,7 @@ pb_status spgemm_plan_info(const pb_plan *p, pb_plan_info *info) {
     info->flop = (int64_t)p->h.flop;
     info->slots = (int64_t)p->h.slots;
     info->run_align = p->align;
+    info->row_count = p->rowcount;
     info->nbins = (int64_t)p->h.nbins;
     info->max_bin_tuples = p->T;
     info->max_row_flop = (int64_t)p->h.maxrow;

@@ -111,6 +111,34 @@ def test_tune_struct_layout():
     assert ctypes.sizeof(B.PbTune) == 32
     assert B.PbTune.round_tuples.offset == 8
     assert B.PbTune.run_align.offset == 16
+    assert B.PbTune.row_count.offset == 20
+    assert ctypes.sizeof(B.PbPlanInfo) % 8 == 0
+
+
+def test_bad_row_count(lib):
+    t = B.PbTune()
+    t.row_count = 3
+    rc, _ = _symbolic(lib, _fake(10, 5, 3), _fake(5, 7, 3), tune=ctypes.byref(t))
+    assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
+    # row buckets need at most 2^25 rows
+    t.row_count = 2
+    rc, _ = _symbolic(lib, _fake((1 << 25) + 1, 5, 3), _fake(5, 7, 3), tune=ctypes.byref(t))
+    assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
+
+
+def test_row_bucket_workspace(lib):
+    """The row-bucket symbolic step needs its histogram and entry records in
+    the symbolic workspace (8 bytes per entry of A on top of the atomic form)."""
+    sizes = {}
+    for mode in (1, 2):
+        t = B.PbTune()
+        t.row_count = mode
+        rc, need = _symbolic(lib, _fake(1000, 500, 3000), _fake(500, 700, 3000), tune=ctypes.byref(t))
+        assert rc == 0
+        sizes[mode] = need
+    assert sizes[2] >= sizes[1] + 8 * 3000
+    rc, auto = _symbolic(lib, _fake(1000, 500, 3000), _fake(500, 700, 3000))
+    assert rc == 0 and auto == sizes[2]
 
 
 def test_bad_run_align(lib):

@@ -263,3 +263,69 @@ def test_run_alignment(pb, align):
     assert info["slots"] == int(np.sum(na * ((nb + align - 1) // align * align)))
     plan.close()
 
+
+
+def _plan_info(pb, A, B, precision, tune):
+    import torch
+
+    nsym = pb.spgemm_symbolic(A, B, precision, tune)
+    plan = pb.spgemm_symbolic(A, B, precision, tune, sym_ws=torch.empty(nsym, dtype=torch.uint8, device="cuda"))
+    info = plan.info()
+    plan.close()
+    return info
+
+
+@pytest.mark.parametrize("row_count", [1, 2])
+def test_row_count_modes(pb, row_count):
+    """Per-row flop and run offsets by device atomics (1) or by row buckets
+    (2): C is the same, and so are the plan's slots, bins and row maxima.
+    The inputs span several 4096-row buckets, long columns of A (taken by a
+    whole wave) and empty rows and columns."""
+    cases = [er_problem(30011, 16, 21, 22, values="signed"),
+             (random_sparse(9000, 700, 0.002, 11, "csc", values="signed", dense_rows=(17, 8999),
+                            empty_cols=(0, 5, 699)),
+              random_sparse(700, 2500, 0.001, 12, "csr", values="signed", dense_cols=(3,), empty_rows=(2, 600)))]
+    for i, (a, b) in enumerate(cases):
+        _say(f"row_count={row_count} case {i}")
+        ref = oracle.spgemm(a, b)
+        A, B = pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)
+        for prec in ("f64", "f32c"):
+            _compare(pb.spgemm(A, B, precision=prec, tune={"row_count": row_count}).to_host(), ref, prec)
+        info = _plan_info(pb, A, B, "f64", {"row_count": row_count})
+        other = _plan_info(pb, A, B, "f64", {"row_count": 3 - row_count})
+        assert info["row_count"] == row_count and other["row_count"] == 3 - row_count
+        for key in ("flop", "slots", "nbins", "max_bin_tuples", "max_row_flop"):
+            assert info[key] == other[key], key
+    # auto picks row buckets
+    assert _plan_info(pb, A, B, "f64", None)["row_count"] == 2
+
+
+def test_row_bucket_run_wider_than_field(pb):
+    """A row of B with more than 2^20 entries: its runs' slot count does not
+    fit the bucket records' 20-bit field and is looked up from B's row
+    pointers instead.  The three rows of C it reaches are far wider than the
+    tile (column windows, dense accumulation)."""
+    n = (1 << 20) + 5
+    rng = np.random.default_rng(31)
+    # B: row 0 holds every column but 0 and 7; row 1 holds 10; row 2 is empty
+    r0 = np.setdiff1d(np.arange(n, dtype=np.int32), np.array([0, 7], dtype=np.int32))
+    r1 = np.sort(rng.choice(n, 10, replace=False)).astype(np.int32)
+    bptr = np.array([0, r0.size, r0.size + r1.size, r0.size + r1.size], dtype=np.int64)
+    b = Csx(3, n, bptr, np.concatenate([r0, r1]), rng.uniform(0, 1, r0.size + r1.size), "csr")
+    # A: column 0 has 3 entries in two row buckets, column 1 has 40 (a long
+    # column), column 2 has 5 (its B row is empty)
+    m = 5000
+    c0 = np.array([5, 4100, 4999], dtype=np.int32)
+    c1 = np.sort(rng.choice(m, 40, replace=False)).astype(np.int32)
+    c2 = np.sort(rng.choice(m, 5, replace=False)).astype(np.int32)
+    aptr = np.array([0, 3, 43, 48], dtype=np.int64)
+    a = Csx(m, 3, aptr, np.concatenate([c0, c1, c2]), rng.uniform(0, 1, 48), "csc")
+    ref = oracle.spgemm(a, b)
+    A, B = pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)
+    for prec in ("f64", "f32c"):
+        _say(f"B row of 2^20 entries, row buckets, {prec}")
+        got = pb.spgemm(A, B, precision=prec, tune={"row_count": 2}).to_host()
+        _compare(got, ref, prec)
+    info = _plan_info(pb, A, B, "f64", {"row_count": 2})
+    atom = _plan_info(pb, A, B, "f64", {"row_count": 1})
+    assert info["row_count"] == 2 and info["slots"] == atom["slots"] and info["max_row_flop"] == atom["max_row_flop"]
