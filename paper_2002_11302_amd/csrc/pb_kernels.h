@@ -160,117 +160,202 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
 
 // ---------------------------------------------------------------------------
 // Per-row flop and run offsets without device atomics (products with fewer
-// than 2^32 entries in A and in B).  The rows are cut into buckets of
-// kRowBucketRows consecutive rows.  A counting sort first distributes the
-// entries of A to their row's bucket (per-workgroup LDS histogram over a
-// contiguous range of columns, a scan of the bucket-major histogram, then a
-// scatter at LDS cursors); one workgroup per bucket then adds each entry's
-// run slots to its row's LDS counter, and the fetched value is the entry's
-// run offset.  Same result as k_rowflop up to the order of the runs in a row.
+// than 2^32 entries in A and at most 2^25 rows).  The rows are cut into
+// buckets of kRowBucketRows consecutive rows.  A counting sort distributes
+// the entries of A to their row's bucket: each workgroup of the distribution
+// takes a contiguous range of entries (read in order, so every pass over
+// them is coalesced), builds an LDS histogram of their buckets, a scan of
+// the bucket-major histogram gives every (bucket, workgroup) pair its place,
+// and a second pass writes one record per entry there (and the record's
+// place, per entry).  One workgroup per bucket adds each record's run slots
+// to its row's LDS counter; the fetched value, the run's offset inside the
+// row, goes back into the record.  A last pass over the entry ranges copies
+// each entry's offset from its record: the records of one range sit in one
+// short segment per bucket, so these reads, like every write, are whole
+// lines.  Same result as k_rowflop up to the order of the runs in a row.
 constexpr int kRowBucketBits = 12;
 constexpr int kRowBucketRows = 1 << kRowBucketBits;
-constexpr int kMaxRowBuckets = 8192;           // LDS histogram of the distribution
-constexpr uint32_t kRunField = 0xfffffu;       // 20-bit run-slot field; saturated:
-                                               // runpos holds the column instead
+constexpr int kMaxRowBuckets = 8192;      // LDS histogram of the distribution
+constexpr int kBucketBlock = 512;         // threads of the distribution passes
+constexpr int kBucketCols = 4032;         // columns of a range held in LDS
+constexpr uint32_t kRunField = 0xfffffu;  // 20-bit run-slot field; saturated:
+                                          // recomputed from B's row pointers
 struct RowBucketArgs {
-    int64_t K;
+    int64_t K, nnz;
     const int64_t *acp, *brp;
     const int32_t *ari;
     int align;
-    int cpt;         // columns per thread of the distribution passes
-    int nbkt, ngrp;  // buckets; workgroups of the distribution passes
-    uint32_t *hist;  // nbkt x ngrp counts (bucket-major), then their scan
-    uint2 *rec;      // per entry, bucket order: (entry, row in bucket | slots << 12)
+    int64_t epw;      // entries per workgroup of the distribution passes
+    int nbkt, ngrp;   // buckets; workgroups of the distribution passes
+    int64_t cpw;      // columns per workgroup for the flop and range starts
+    int32_t *kstart;  // [ngrp + 1]: column holding entry g * epw; [ngrp]: the
+                      // column holding the last entry
+    uint32_t *hist;   // nbkt x ngrp counts (bucket-major), then their scan
+    uint64_t *gflop;  // [ngrp]: multiplications of each workgroup's columns
+    uint2 *rec;       // bucket order: (row in bucket | slots << 12, column),
+                      // then (same, run offset in the row)
+    uint32_t *posof;  // per entry: its record
     uint32_t *runpos;
     uint64_t *rowflop;
     SymInfo *info;
 };
 
-// Visits every A entry of this workgroup's columns: f(e, row, slots, k).
-// One thread per column; columns longer than 32 entries are taken by the
-// whole wave, lanes striding over the column.  Returns the multiplications
-// of this thread's columns.
-template <int BLOCK, class F>
-__device__ __forceinline__ uint64_t visit_entries(const RowBucketArgs &a, F &&f) {
-    uint64_t flop = 0;
-    const uint32_t lane = lane_id();
-    for (int i = 0; i < a.cpt; ++i) {
-        const int64_t k = ((int64_t)blockIdx.x * a.cpt + i) * BLOCK + threadIdx.x;
-        int64_t a0 = 0, na = 0, nb = 0;
-        if (k < a.K) {
-            a0 = a.acp[k];
-            na = a.acp[k + 1] - a0;
-            nb = a.brp[k + 1] - a.brp[k];
-            if (nb == 0) na = 0;
-        }
-        flop += (uint64_t)(na * nb);
-        const int64_t pnb = run_slots(nb, a.align);
-        const bool longcol = na > 32;
-        if (!longcol)
-            for (int64_t e = a0; e < a0 + na; ++e) f(e, a.ari[e], pnb, k);
-        uint64_t mask = ballot(longcol);
-        while (mask) {
-            const int L = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const int64_t la0 = __shfl(a0, L, kWave);
-            const int64_t lna = __shfl(na, L, kWave);
-            const int64_t lnb = __shfl(pnb, L, kWave);
-            const int64_t lk = __shfl(k, L, kWave);
-            for (int64_t e = la0 + lane; e < la0 + lna; e += kWave) f(e, a.ari[e], lnb, lk);
-        }
-    }
-    return flop;
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t *lds) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    for (int i = 0; i < BLOCK / kWave; ++i) t += lds[i];
+    __syncthreads();
+    return t;
 }
 
-// (dynamic LDS: one counter per bucket)
+// Pass 1 (dynamic LDS: one counter per bucket).  Also, over a slice of the
+// columns: their multiplications (Algorithm 3) and each entry range's first
+// column.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_hist(RowBucketArgs a) {
     extern __shared__ uint32_t s_h[];
+    __shared__ uint64_t s_red[BLOCK / kWave];
     for (int b = threadIdx.x; b < a.nbkt; b += BLOCK) s_h[b] = 0;
     __syncthreads();
-    uint64_t f = visit_entries<BLOCK>(a, [&](int64_t, int32_t r, int64_t, int64_t) {
-        atomicAdd(&s_h[r >> kRowBucketBits], 1u);
-    });
-    // Algorithm 3's multiplication count, one atomic per wave
+    const int64_t e0 = blockIdx.x * a.epw;
+    const int64_t e1 = e0 + a.epw < a.nnz ? e0 + a.epw : a.nnz;
+    constexpr int U = 4;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)BLOCK * U) {
+        int32_t r[U];
 #pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) f += __shfl_xor(f, d, kWave);
-    if (lane_id() == 0 && f) atomic_add_agent(&a.info->flop, f);
-    __syncthreads();
+        for (int u = 0; u < U; ++u) r[u] = e + u * BLOCK < e1 ? a.ari[e + u * BLOCK] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (r[u] >= 0) atomicAdd(&s_h[r[u] >> kRowBucketBits], 1u);
+    }
+    uint64_t f = 0;
+    const int64_t c1 = (blockIdx.x + 1) * a.cpw < a.K ? (blockIdx.x + 1) * a.cpw : a.K;
+    for (int64_t c = blockIdx.x * a.cpw + threadIdx.x; c < c1; c += BLOCK) {
+        const int64_t a0 = a.acp[c], a1 = a.acp[c + 1];
+        f += (uint64_t)((a1 - a0) * (a.brp[c + 1] - a.brp[c]));
+        for (int64_t g = (a0 + a.epw - 1) / a.epw; g * a.epw < a1; ++g) a.kstart[g] = (int32_t)c;
+        if (a0 <= a.nnz - 1 && a.nnz - 1 < a1) a.kstart[a.ngrp] = (int32_t)c;
+    }
+    f = block_sum<BLOCK>(f, s_red);
+    if (threadIdx.x == 0) a.gflop[blockIdx.x] = f;
     for (int b = threadIdx.x; b < a.nbkt; b += BLOCK) a.hist[(int64_t)b * a.ngrp + blockIdx.x] = s_h[b];
 }
 
+// Pass 2: the same entry ranges; an entry's column comes from a binary
+// search of the range's column starts in LDS (or, for a range spanning more
+// than kBucketCols columns, from walking those columns).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(RowBucketArgs a) {
     extern __shared__ uint32_t s_cur[];
+    __shared__ uint32_t s_off[kBucketCols + 1];
+    __shared__ uint32_t s_slots[kBucketCols];
     for (int b = threadIdx.x; b < a.nbkt; b += BLOCK) s_cur[b] = a.hist[(int64_t)b * a.ngrp + blockIdx.x];
-    __syncthreads();
-    visit_entries<BLOCK>(a, [&](int64_t e, int32_t r, int64_t slots, int64_t k) {
+    const int64_t e0 = blockIdx.x * a.epw;
+    const int64_t e1 = e0 + a.epw < a.nnz ? e0 + a.epw : a.nnz;
+    const int64_t k0 = a.kstart[blockIdx.x], kend = a.kstart[blockIdx.x + 1];
+    const int64_t nc = kend - k0 + 1;
+    auto put = [&](int64_t e, int32_t r, uint32_t field, int64_t k) {
         const uint32_t pos = atomicAdd(&s_cur[r >> kRowBucketBits], 1u);
-        const uint32_t field = slots < (int64_t)kRunField ? (uint32_t)slots : kRunField;
-        if (field == kRunField) a.runpos[e] = (uint32_t)k;
-        a.rec[pos] = make_uint2((uint32_t)e, (uint32_t)(r & (kRowBucketRows - 1)) | field << kRowBucketBits);
-    });
+        a.rec[pos] = make_uint2((uint32_t)(r & (kRowBucketRows - 1)) | field << kRowBucketBits, (uint32_t)k);
+        a.posof[e] = pos;
+    };
+    if (nc <= kBucketCols) {
+        for (int64_t i = threadIdx.x; i <= nc; i += BLOCK) {
+            const int64_t c = k0 + i;
+            const int64_t o = a.acp[c] - e0;
+            s_off[i] = (uint32_t)(o < 0 ? 0 : (o > a.epw ? a.epw : o));
+            if (i < nc) {
+                const int64_t sl = run_slots(a.brp[c + 1] - a.brp[c], a.align);
+                s_slots[i] = sl < (int64_t)kRunField ? (uint32_t)sl : kRunField;
+            }
+        }
+        __syncthreads();
+        constexpr int U = 4;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)BLOCK * U) {
+            int32_t r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = e + u * BLOCK < e1 ? a.ari[e + u * BLOCK] : -1;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (r[u] < 0) continue;
+                const uint32_t rel = (uint32_t)(e + u * BLOCK - e0);
+                // s_off[lo] <= rel < s_off[hi]
+                int lo = 0, hi = (int)nc;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= rel) lo = mid;
+                    else hi = mid;
+                }
+                put(e + u * BLOCK, r[u], s_slots[lo], k0 + lo);
+            }
+        }
+    } else {
+        __syncthreads();
+        for (int64_t c = k0 + threadIdx.x; c <= kend; c += BLOCK) {
+            const int64_t c0 = a.acp[c], c1 = a.acp[c + 1];
+            const int64_t sl = run_slots(a.brp[c + 1] - a.brp[c], a.align);
+            const uint32_t field = sl < (int64_t)kRunField ? (uint32_t)sl : kRunField;
+            for (int64_t e = c0 > e0 ? c0 : e0; e < (c1 < e1 ? c1 : e1); ++e) put(e, a.ari[e], field, c);
+        }
+    }
 }
 
+// Pass 3: one workgroup per bucket; block 0 also adds up the multiplication
+// count.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t m) {
     __shared__ unsigned long long s_cnt[kRowBucketRows];
+    __shared__ uint64_t s_red[BLOCK / kWave];
     for (int i = threadIdx.x; i < kRowBucketRows; i += BLOCK) s_cnt[i] = 0;
-    __syncthreads();
     const int64_t b = blockIdx.x;
+    if (b == 0) {
+        uint64_t f = 0;
+        for (int g = threadIdx.x; g < a.ngrp; g += BLOCK) f += a.gflop[g];
+        f = block_sum<BLOCK>(f, s_red);
+        if (threadIdx.x == 0) a.info->flop = f;
+    }
+    __syncthreads();
     const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
-    for (uint32_t p = p0 + threadIdx.x; p < p1; p += BLOCK) {
-        const uint2 r = a.rec[p];
-        uint64_t slots = r.y >> kRowBucketBits;
-        if (slots == kRunField) {
-            const uint32_t k = a.runpos[r.x];
-            slots = (uint64_t)run_slots(a.brp[k + 1] - a.brp[k], a.align);
+    constexpr int U = 4;
+    for (int64_t p = (int64_t)p0 + threadIdx.x; p < p1; p += (int64_t)BLOCK * U) {
+        uint2 rc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) rc[u] = p + u * BLOCK < p1 ? a.rec[p + u * BLOCK] : make_uint2(0, 0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p + u * BLOCK >= p1) break;
+            uint64_t slots = rc[u].x >> kRowBucketBits;
+            if (slots == kRunField) slots = (uint64_t)run_slots(a.brp[rc[u].y + 1] - a.brp[rc[u].y], a.align);
+            const uint64_t old = atomicAdd(&s_cnt[rc[u].x & (kRowBucketRows - 1)], (unsigned long long)slots);
+            a.rec[p + u * BLOCK] = make_uint2(rc[u].x, (uint32_t)old);
         }
-        a.runpos[r.x] = (uint32_t)atomicAdd(&s_cnt[r.y & (kRowBucketRows - 1)], (unsigned long long)slots);
     }
     __syncthreads();
     const int64_t r0 = b << kRowBucketBits;
     for (int i = threadIdx.x; i < kRowBucketRows && r0 + i < m; i += BLOCK) a.rowflop[r0 + i] = s_cnt[i];
+}
+
+// Pass 4: each entry's run offset from its record.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_offsets(RowBucketArgs a) {
+    const int64_t e0 = blockIdx.x * a.epw;
+    const int64_t e1 = e0 + a.epw < a.nnz ? e0 + a.epw : a.nnz;
+    constexpr int U = 4;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)BLOCK * U) {
+        uint32_t ps[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ps[u] = e + u * BLOCK < e1 ? a.posof[e + u * BLOCK] : 0u;
+        uint32_t off[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) off[u] = a.rec[ps[u]].y;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e + u * BLOCK < e1) a.runpos[e + u * BLOCK] = off[u];
+    }
 }
 
 // Exclusive scan of the bucket-major histogram, in place (total at [n]).

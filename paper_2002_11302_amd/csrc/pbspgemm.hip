@@ -228,9 +228,13 @@ struct SymLayout {
     int64_t *binoff;
     // row buckets (rowcount 2)
     uint64_t *stH;
+    int32_t *kstart;
     uint32_t *hist;
+    uint64_t *gflop;
     uint2 *rec;
-    int nbkt, ngrp, cpt;
+    uint32_t *posof;
+    int nbkt, ngrp;
+    int64_t epw, cpw;
     // batch only
     ProbDesc *pdesc;
     int64_t *prob_row0;
@@ -241,24 +245,28 @@ struct SymLayout {
 };
 
 // Shape of the row-bucket distribution: buckets of kRowBucketRows rows;
-// at most 2048 workgroups of 256 threads, each over a contiguous range of
-// columns (cpt columns per thread).
+// workgroups over ranges of kBucketEntries entries of A (the histogram then
+// has at most nnz(A) * m / 2^25 <= nnz(A) counts).
+constexpr int64_t kBucketEntries = 8192;
 struct BucketShape {
-    int nbkt, ngrp, cpt;
+    int nbkt, ngrp;
+    int64_t epw, cpw;
     int64_t nhist() const { return (int64_t)nbkt * ngrp; }
 };
-BucketShape bucket_shape(int64_t m, int64_t k) {
+BucketShape bucket_shape(int64_t m, int64_t k, int64_t nnza) {
     BucketShape s{};
     s.nbkt = (int)ceil_div(m, kRowBucketRows);
-    s.cpt = (int)std::max<int64_t>(1, ceil_div(k, (int64_t)256 * 2048));
-    s.ngrp = (int)ceil_div(k, (int64_t)256 * s.cpt);
+    s.epw = kBucketEntries;
+    s.ngrp = (int)ceil_div(nnza, s.epw);
+    s.cpw = s.ngrp ? ceil_div(k, (int64_t)s.ngrp) : 0;
     return s;
 }
 
 // Row buckets when A has fewer than 2^32 entries (32-bit positions) and the
 // bucket histogram fits LDS; device atomics otherwise.
 int pick_rowcount(int requested, int64_t m, int64_t k, int64_t nnza) {
-    const bool ok = m > 0 && k > 0 && nnza < ((int64_t)1 << 32) && ceil_div(m, kRowBucketRows) <= kMaxRowBuckets;
+    const bool ok = m > 0 && k > 0 && nnza > 0 && nnza < ((int64_t)1 << 32) &&
+                    ceil_div(m, kRowBucketRows) <= kMaxRowBuckets;
     if (requested == 1) return 1;
     if (requested == 2) return ok ? 2 : -1;
     return ok ? 2 : 1;
@@ -268,10 +276,11 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
     Carver cv(base);
     SymLayout L{};
     BucketShape bs{};
-    if (rowcount == 2) bs = bucket_shape(m, k);
+    if (rowcount == 2) bs = bucket_shape(m, k, nnza);
     L.nbkt = bs.nbkt;
     L.ngrp = bs.ngrp;
-    L.cpt = bs.cpt;
+    L.epw = bs.epw;
+    L.cpw = bs.cpw;
     // zeroed region first
     L.info = cv.take<SymInfo>(1);
     L.tickets = cv.take<uint32_t>(4);
@@ -287,8 +296,11 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
     L.binrow0 = cv.take<int32_t>(m + 1);
     L.binoff = cv.take<int64_t>(m + 1);
     if (rowcount == 2) {
+        L.kstart = cv.take<int32_t>(bs.ngrp + 1);
         L.hist = cv.take<uint32_t>(bs.nhist() + 1);
+        L.gflop = cv.take<uint64_t>(bs.ngrp);
         L.rec = cv.take<uint2>(nnza);
+        L.posof = cv.take<uint32_t>(nnza);
     }
     if (count > 1) {
         L.pdesc = cv.take<ProbDesc>(count);
@@ -363,18 +375,21 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
         PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp, p->align}, ColFlopDst{{}, L.F, k, L.info}, L.stF,
                                   &L.tickets[0], &L.info->err, st, "flop scan"));
         if (p->rowcount == 2) {
-            const RowBucketArgs ra{k,      acp,    brp,    ari,   p->align, L.cpt, L.nbkt,
-                                   L.ngrp, L.hist, L.rec, L.runpos, L.R,  L.info};
+            const RowBucketArgs ra{k,      p->nnzA, acp,      brp,    ari,     p->align, L.epw,    L.nbkt, L.ngrp,
+                                   L.cpw,  L.kstart, L.hist, L.gflop, L.rec,  L.posof,  L.runpos, L.R,    L.info};
             const int64_t nh = (int64_t)L.nbkt * L.ngrp;
             const size_t lds = (size_t)L.nbkt * sizeof(uint32_t);
-            hipLaunchKernelGGL(k_bucket_hist<256>, dim3((unsigned)L.ngrp), dim3(256), lds, st, ra);
+            const dim3 grid((unsigned)L.ngrp), block(kBucketBlock);
+            hipLaunchKernelGGL(k_bucket_hist<kBucketBlock>, grid, block, lds, st, ra);
             PB_LAUNCHED("bucket histogram");
             PB_TRY(launch_scan<SumOp>(nh, HistSrc{L.hist}, HistDst{{}, L.hist, nh}, L.stH, &L.tickets[3],
                                       &L.info->err, st, "bucket scan"));
-            hipLaunchKernelGGL(k_bucket_scatter<256>, dim3((unsigned)L.ngrp), dim3(256), lds, st, ra);
+            hipLaunchKernelGGL(k_bucket_scatter<kBucketBlock>, grid, block, lds, st, ra);
             PB_LAUNCHED("bucket scatter");
             hipLaunchKernelGGL(k_bucket_count<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
             PB_LAUNCHED("bucket count");
+            hipLaunchKernelGGL(k_bucket_offsets<kBucketBlock>, grid, block, 0, st, ra);
+            PB_LAUNCHED("bucket offsets");
         } else {
             hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp,
                                p->align, L.R, L.runpos, L.info);

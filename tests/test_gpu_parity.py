@@ -279,12 +279,17 @@ def _plan_info(pb, A, B, precision, tune):
 def test_row_count_modes(pb, row_count):
     """Per-row flop and run offsets by device atomics (1) or by row buckets
     (2): C is the same, and so are the plan's slots, bins and row maxima.
-    The inputs span several 4096-row buckets, long columns of A (taken by a
-    whole wave) and empty rows and columns."""
+    The inputs span several 4096-row buckets, dense rows, empty rows and
+    columns, and columns so sparse that a range of entries covers tens of
+    thousands of columns."""
     cases = [er_problem(30011, 16, 21, 22, values="signed"),
              (random_sparse(9000, 700, 0.002, 11, "csc", values="signed", dense_rows=(17, 8999),
                             empty_cols=(0, 5, 699)),
-              random_sparse(700, 2500, 0.001, 12, "csr", values="signed", dense_cols=(3,), empty_rows=(2, 600)))]
+              random_sparse(700, 2500, 0.001, 12, "csr", values="signed", dense_cols=(3,), empty_rows=(2, 600))),
+             # about 0.2 entries per column of A: each range of entries spans
+             # more columns than the LDS column table holds
+             (random_sparse(9000, 100000, 2e-5, 13, "csc", values="signed"),
+              random_sparse(100000, 3000, 0.003, 14, "csr", values="signed"))]
     for i, (a, b) in enumerate(cases):
         _say(f"row_count={row_count} case {i}")
         ref = oracle.spgemm(a, b)
