@@ -953,7 +953,7 @@ template <int BLOCK, int TMAX, class VT>
 __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     constexpr int NW = BLOCK / kWave;
     constexpr int IPT = TMAX / BLOCK;
-    constexpr int NB = TMAX / 2;  // buckets of the one-pass path (hist region)
+    constexpr int NB = TMAX >= 4096 ? TMAX : TMAX / 2;  // buckets of the one-pass path
     constexpr int LOG_NB = (NB >= 4096) ? 12 : (NB >= 2048) ? 11 : (NB >= 1024) ? 10 : 9;
     static_assert((1 << LOG_NB) == NB, "NB must be a power of two");
     static_assert(NW >= 4, "digit scan uses the first 256 threads");
