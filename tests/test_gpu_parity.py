@@ -334,3 +334,28 @@ def test_row_bucket_run_wider_than_field(pb):
     info = _plan_info(pb, A, B, "f64", {"row_count": 2})
     atom = _plan_info(pb, A, B, "f64", {"row_count": 1})
     assert info["row_count"] == 2 and info["slots"] == atom["slots"] and info["max_row_flop"] == atom["max_row_flop"]
+
+
+@pytest.mark.parametrize("run", [30, 50])
+def test_sort_crowded_buckets(pb, run):
+    """Bins whose keys spread over 2^20 columns except one B row of `run`
+    consecutive columns: every row of C that reaches it puts `run` keys in
+    one sort bucket.  30 keys take the per-bucket ranking fallback (more than
+    a thread sorts in registers), 50 the radix-sort path."""
+    _say(f"crowded buckets, run of {run}")
+    rng = np.random.default_rng(run)
+    n, kdim, m, d = 1 << 20, 8192, 8192, 8
+    rows = []
+    for k in range(kdim):
+        if k % 512 == 7:
+            rows.append(np.arange(1000, 1000 + run, dtype=np.int32))
+        else:
+            rows.append(np.sort(rng.choice(n, d, replace=False)).astype(np.int32))
+    bptr = np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64)
+    b = Csx(kdim, n, bptr, np.concatenate(rows), rng.uniform(0, 1, int(bptr[-1])), "csr")
+    cols = [np.sort(rng.choice(m, d, replace=False)).astype(np.int32) for _ in range(kdim)]
+    aptr = np.concatenate([[0], np.cumsum([c.size for c in cols])]).astype(np.int64)
+    a = Csx(m, kdim, aptr, np.concatenate(cols), rng.uniform(0, 1, int(aptr[-1])), "csc")
+    ref = oracle.spgemm(a, b)
+    for prec in ("f64", "f32c"):
+        _compare(_run(pb, a, b, prec), ref, prec)
