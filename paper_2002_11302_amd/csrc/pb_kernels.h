@@ -1017,14 +1017,20 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     uint32_t rk[IPT];
     VT rv[IPT];
     uint32_t kmin = 0xffffffffu, kmax = 0, nreal = 0;
+    // every load is issued before any is used: keys first, so the key
+    // phases below wait only for them while the values are still arriving
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-        rk[i] = kSentinel;
-        if (p < N) {
-            rk[i] = gk[p];
-            rv[i] = gvb[p];
-        }
+        rk[i] = p < N ? gk[p] : kSentinel;
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+        rv[i] = gvb[p < N ? p : N - 1];  // in range for every lane (N >= 1); parked only for p < N
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
         const bool real = rk[i] != kSentinel;
         if (real) {
             kmin = rk[i] < kmin ? rk[i] : kmin;
