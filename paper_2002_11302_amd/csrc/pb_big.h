@@ -166,17 +166,22 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
         uint32_t col[PER], rank[PER];
         bool real[PER];
         VT val[PER];
+        // unconditional loads (the last tuple stands in past the end) overlap
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int q = u * BLOCK + threadIdx.x;
-            col[u] = 0;
-            real[u] = false;
-            if (q < nsub) {
-                const uint32_t key = a.keys[s0 + q];
-                real[u] = key != kSentinel;  // padding slots are dropped here
-                col[u] = key & colmask;
-                val[u] = gv[s0 + q];
-            }
+            col[u] = a.keys[s0 + (q < nsub ? q : nsub - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = u * BLOCK + threadIdx.x;
+            val[u] = gv[s0 + (q < nsub ? q : nsub - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = u * BLOCK + threadIdx.x;
+            real[u] = q < nsub && col[u] != kSentinel;  // padding slots are dropped here
+            col[u] &= colmask;
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u)
@@ -308,10 +313,26 @@ __global__ __launch_bounds__(BLOCK) void k_dense(DenseArgs a) {
         if (OUT)
             for (int x = threadIdx.x; x < ncol; x += BLOCK) acc[x] = 0.0;
         __syncthreads();
-        for (int64_t p = s + threadIdx.x; p < e; p += BLOCK) {
-            const uint32_t c = a.keys2[p] & wmask;
-            atomicOr(&bits[c >> 5], 1u << (c & 31));
-            if (OUT) atomicAdd(&acc[c], (double)gv[p]);
+        constexpr int U = 8;  // tuples loaded per thread before they are added
+        for (int64_t p0 = s + threadIdx.x; p0 < e; p0 += (int64_t)BLOCK * U) {
+            uint32_t kc[U];
+            VT vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = p0 + u * BLOCK < e ? p0 + u * BLOCK : e - 1;
+                kc[u] = a.keys2[q];
+                if (OUT) vv[u] = gv[q];
+            }
+            // lanes past the end repeat the last tuple with nothing to add
+            // (its column's bit is set by its own lane), so every use of
+            // the loads is unconditional and they stay overlapped
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = p0 + u * BLOCK < e;
+                const uint32_t c = kc[u] & wmask;
+                atomicOr(&bits[c >> 5], in ? 1u << (c & 31) : 0u);
+                if (OUT) atomicAdd(&acc[c], in ? (double)vv[u] : 0.0);
+            }
         }
         __syncthreads();
         const uint32_t byte = (bits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 8)) & 0xffu;

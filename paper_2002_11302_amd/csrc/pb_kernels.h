@@ -227,10 +227,10 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_hist(RowBucketArgs a) {
     for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)BLOCK * U) {
         int32_t r[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = e + u * BLOCK < e1 ? a.ari[e + u * BLOCK] : -1;
+        for (int u = 0; u < U; ++u) r[u] = a.ari[e + u * BLOCK < e1 ? e + u * BLOCK : e1 - 1];  // loads overlap
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (r[u] >= 0) atomicAdd(&s_h[r[u] >> kRowBucketBits], 1u);
+            if (e + u * BLOCK < e1) atomicAdd(&s_h[r[u] >> kRowBucketBits], 1u);
     }
     uint64_t f = 0;
     const int64_t c1 = (blockIdx.x + 1) * a.cpw < a.K ? (blockIdx.x + 1) * a.cpw : a.K;
@@ -278,10 +278,10 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(RowBucketArgs a) {
         for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)BLOCK * U) {
             int32_t r[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) r[u] = e + u * BLOCK < e1 ? a.ari[e + u * BLOCK] : -1;
+            for (int u = 0; u < U; ++u) r[u] = a.ari[e + u * BLOCK < e1 ? e + u * BLOCK : e1 - 1];  // loads overlap
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (r[u] < 0) continue;
+                if (e + u * BLOCK >= e1) continue;
                 const uint32_t rel = (uint32_t)(e + u * BLOCK - e0);
                 // s_off[lo] <= rel < s_off[hi]
                 int lo = 0, hi = (int)nc;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t
     for (int64_t p = (int64_t)p0 + threadIdx.x; p < p1; p += (int64_t)BLOCK * U) {
         uint2 rc[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) rc[u] = p + u * BLOCK < p1 ? a.rec[p + u * BLOCK] : make_uint2(0, 0);
+        for (int u = 0; u < U; ++u) rc[u] = a.rec[p + u * BLOCK < p1 ? p + u * BLOCK : p1 - 1];  // unconditional loads overlap
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (p + u * BLOCK >= p1) break;
