@@ -706,18 +706,23 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
         if (threadIdx.x == 0) atomic_or_agent(a.err, (uint32_t)kErrTile);
         return;
     }
-    for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
-    __syncthreads();
+    if (N == 0) {  // rows without tuples
+        for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 - a.row_base + x] = 0;
+        return;
+    }
     const uint32_t *gk = a.keys + toff;
     const int cb = a.cb;
     constexpr int IPT = TMAX / BLOCK;
     uint32_t kr[IPT];
-    // all loads first, so their latencies overlap
+    // all loads first (unconditional: the last key stands in past the end),
+    // so their latencies overlap each other and the table's clearing
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = i * BLOCK + threadIdx.x;
-        kr[i] = p < N ? gk[p] : EMPTY;
+        kr[i] = gk[p < N ? p : N - 1];
     }
+    for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const uint32_t key = kr[i];
