@@ -546,6 +546,106 @@ __device__ __forceinline__ void divmod_u(int64_t x, int64_t d, int64_t &q, int64
     }
 }
 
+// Chunks that span many short columns: each lane finds its own column.  The
+// wave holds the facts of 64 consecutive columns, one per lane (where the
+// column's tuples start in the flop space, B's row, A's column start), and
+// takes 64 consecutive tuples per step; a lane's column is the last one
+// starting at or before its tuple (a binary search over the lanes), and its
+// (A entry, B entry) pair comes from a divmod by the column's run slots.
+constexpr int kShortCols = 8;  // a chunk spanning more columns takes this path
+
+template <int W, class VT>
+__device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, const int64_t *__restrict__ acp,
+                                             const int64_t *__restrict__ astart, const int64_t *__restrict__ brp,
+                                             const int32_t *__restrict__ ari, const uint32_t *__restrict__ runpos,
+                                             const RowTab *__restrict__ rowtab, const double *__restrict__ avv,
+                                             const int32_t *__restrict__ bci, const double *__restrict__ bvals,
+                                             uint32_t *__restrict__ keys, VT *__restrict__ vals,
+                                             uint32_t *__restrict__ err, int cb, int64_t flop, int64_t slot0,
+                                             int align, int64_t K, int64_t kb, int64_t t, const int64_t t1) {
+    const int lane = (int)lane_id();
+    bool bad = false;
+    while (t < t1) {
+        const int64_t kk = kb + lane;
+        int64_t f0 = INT64_MAX;  // past the columns: never owns a tuple
+        int64_t as = 0;
+        uint32_t bs = 0, nbt = 0;
+        if (kk < K) {
+            f0 = F[kk];
+            const int64_t b0 = brp[kk];
+            bs = (uint32_t)b0;
+            nbt = (uint32_t)(brp[kk + 1] - b0);
+            as = astart ? astart[kk] : acp[kk];
+        }
+        const int64_t kn = kb + kWave;
+        const int64_t wend0 = F[kn < K ? kn : K];  // where the next window's first column starts
+        const int64_t wend = wend0 < t1 ? wend0 : t1;
+        constexpr int U = 4;
+        for (int64_t tt = t; tt < wend; tt += U * kWave) {
+            int64_t ii[U], asu[U];
+            uint32_t jj[U], nbu[U], bsu[U];
+            bool on[U], own[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t ts = tt + u * kWave;  // the step's first tuple (wave-uniform)
+                const int64_t d = f0 - ts;
+                const int rel = d < -1 ? -1 : (d > kWave ? kWave : (int)d);
+                int L = 0;
+#pragma unroll
+                for (int s = kWave / 2; s >= 1; s >>= 1)
+                    if (__shfl(rel, L + s, kWave) <= lane) L += s;
+                const int64_t fL = __shfl(f0, L, kWave);
+                nbu[u] = __shfl(nbt, L, kWave);
+                bsu[u] = __shfl(bs, L, kWave);
+                asu[u] = __shfl(as, L, kWave);
+                on[u] = ts + lane < wend;
+                own[u] = on[u] && fL <= ts + lane && nbu[u] > 0;
+                int64_t q = 0, r = 0;
+                if (own[u]) divmod_u(ts + lane - fL, run_slots(nbu[u], align), q, r);
+                ii[u] = q;
+                jj[u] = (uint32_t)r;
+            }
+            int32_t ar[U];
+            uint32_t rp[U], col[U];
+            double av[U], bvv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = own[u] ? asu[u] + ii[u] : 0;
+                // padding slots read the run's last B entry
+                const uint32_t jb = own[u] ? (jj[u] < nbu[u] ? jj[u] : nbu[u] - 1u) : 0u;
+                const uint32_t bi = own[u] ? bsu[u] + jb : 0u;
+                ar[u] = ari[e];
+                rp[u] = runpos[e];
+                av[u] = avv[e];
+                col[u] = (uint32_t)bci[bi];
+                bvv[u] = bvals[bi];
+            }
+            RowTab rt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rt[u] = rowtab[ar[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!on[u]) continue;
+                if (!own[u]) {
+                    bad = true;
+                    continue;
+                }
+                const int64_t slot = rt[u].base - slot0 + (int64_t)rp[u] + jj[u];
+                const bool real = jj[u] < nbu[u];
+                if ((uint64_t)slot < (uint64_t)flop) {
+                    keys[slot] = real ? ((rt[u].rl << cb) | col[u]) : kSentinel;
+                    vals[slot] = real ? (VT)(av[u] * bvv[u]) : (VT)0;
+                } else {
+                    bad = true;
+                }
+            }
+        }
+        if (wend > t) t = wend;
+        kb = kn;
+    }
+    if (bad) atomic_or_agent(err, (uint32_t)kErrBinOverflow);
+}
+
 // One wave per chunk of W tuples.  The wave walks the columns its chunk
 // touches; the column's facts (F[k], where A(:,k) and B(k,:) start, nnz of
 // B(k,:)) are wave-uniform, and each lane takes one tuple of the current
@@ -562,7 +662,7 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
                                             const int32_t *__restrict__ bci, const double *__restrict__ bvals,
                                             uint32_t *__restrict__ keys, VT *__restrict__ vals,
                                             uint32_t *__restrict__ err, int cb, int64_t flop, int64_t slot0,
-                                            int align, int64_t nchunks) {
+                                            int align, int64_t nchunks, int64_t K) {
     const uint32_t lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wave >= nchunks) return;
@@ -570,6 +670,11 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
     const int64_t t1 = (t0 + W < flop) ? t0 + W : flop;
     int64_t k = kstart[wave];
     int64_t t = t0;
+    if (kstart[wave + 1] - k > kShortCols) {
+        expand_lanes<W, VT>(F, acp, astart, brp, ari, runpos, rowtab, avv, bci, bvals, keys, vals, err, cb, flop,
+                            slot0, align, K, k, t0, t1);
+        return;
+    }
     while (t < t1) {
         const int64_t Fk1 = F[k + 1];
         if (Fk1 <= t) {  // column with no tuples left in this chunk
@@ -657,7 +762,7 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
 template <int W, class VT>
 __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
     expand_body<W, VT>(a.F, a.kstart, a.acp, a.astart, a.brp, a.ari, a.runpos, a.rowtab, a.av, a.bci, a.bv, a.keys,
-                       (VT *)a.vals, a.err, a.cb, a.flop, a.slot0, a.align, nchunks);
+                       (VT *)a.vals, a.err, a.cb, a.flop, a.slot0, a.align, nchunks, a.K);
 }
 
 // ---------------------------------------------------------------------------
