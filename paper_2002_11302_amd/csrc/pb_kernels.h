@@ -1107,18 +1107,20 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         return;
     }
     if (N == 0) return;
-    int64_t base;
+    int64_t base, bend;  // the bin's first entry of C and one past its last
     int32_t *colidx = a.colidx;
     void *cvals = a.cvals;
     int64_t capacity = a.capacity;
     if (a.outs) {
         const OutDesc od = a.outs[prob_of_row(a.prob_row0, a.nprob, row0)];
         base = od.rowptr[row0 - od.row0];
+        bend = od.rowptr[row0 + nrows - od.row0];
         colidx = od.colidx;
         cvals = od.val;
         capacity = od.capacity;
     } else {
         base = a.rowptr[row0 - a.row_base];
+        bend = a.rowptr[row0 + nrows - a.row_base];
     }
     const uint32_t *gk = a.keys + toff;
     const VT *gvb = (const VT *)a.vals + toff;
@@ -1138,6 +1140,72 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         rv[i] = gvb[p < N ? p : N - 1];  // in range for every lane (N >= 1); parked only for p < N
+    }
+    // Bins whose keys repeat a lot (at most a quarter of the slots hold
+    // distinct keys; that count is known from C's row pointers): equal keys
+    // are first summed in an LDS hash table, in double, and only the
+    // distinct keys, each with its sum, go on to the sort.
+    {
+        const int64_t D = bend - base;
+        if (D > 0 && 4 * D <= N && D <= TMAX / 4) {
+            constexpr int TSD = TMAX / 2;  // table slots, load factor <= 1/2
+            constexpr int LOG_TSD = (TSD >= 2048) ? 11 : (TSD >= 1024) ? 10 : 9;
+            static_assert((1 << LOG_TSD) == TSD, "table size");
+            static_assert(TSD % BLOCK == 0, "whole slots per thread");
+            uint32_t *tk = (uint32_t *)(smem + OFF_KA);                 // table keys
+            double *tv = (double *)(smem + OFF_KB);                     // table sums
+            uint32_t *ck = (uint32_t *)(smem + OFF_SA);                 // distinct keys
+            double *cs = (double *)(smem + OFF_KB + 4 * TMAX);          // their sums
+            static_assert(OFF_KB + 4 * TMAX + 8 * (TMAX / 4) <= OFF_END, "dedup arrays fit");
+            for (int x = threadIdx.x; x < TSD; x += BLOCK) {
+                tk[x] = kSentinel;
+                tv[x] = 0.0;
+            }
+            __syncthreads();
+            bool full = false;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+                if (p < N && rk[i] != kSentinel) {
+                    uint32_t h = (rk[i] * 0x9E3779B1u) >> (32 - LOG_TSD);
+                    int probes = 0;
+                    while (probes < TSD) {
+                        const uint32_t old = atomicCAS(&tk[h], kSentinel, rk[i]);
+                        if (old == kSentinel || old == rk[i]) break;
+                        h = (h + 1) & (TSD - 1);
+                        ++probes;
+                    }
+                    if (probes < TSD) atomicAdd(&tv[h], (double)rv[i]);
+                    else full = true;  // more distinct keys than the row pointers say
+                }
+            }
+            if (full) atomic_or_agent(a.err, (uint32_t)kErrTile);
+            __syncthreads();
+            constexpr int SPT = TSD / BLOCK;
+            uint32_t occ = 0;
+#pragma unroll
+            for (int x = 0; x < SPT; ++x) occ += tk[threadIdx.x * SPT + x] != kSentinel;
+            uint64_t tot;
+            uint64_t at = block_excl_scan<BLOCK, SumOp>(occ, s_scan, tot);
+#pragma unroll
+            for (int x = 0; x < SPT; ++x) {
+                const int sl = threadIdx.x * SPT + x;
+                if (tk[sl] != kSentinel) {
+                    ck[at] = tk[sl];
+                    cs[at] = tv[sl];
+                    ++at;
+                }
+            }
+            __syncthreads();
+            N = (int)tot;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+                rk[i] = p < N ? ck[p] : kSentinel;
+                rv[i] = p < N ? (VT)cs[p] : (VT)0;
+            }
+            __syncthreads();  // the sort below reuses the LDS
+        }
     }
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {

@@ -359,3 +359,18 @@ def test_sort_crowded_buckets(pb, run):
     ref = oracle.spgemm(a, b)
     for prec in ("f64", "f32c"):
         _compare(_run(pb, a, b, prec), ref, prec)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_sort_heavy_repeats(pb, precision):
+    """Bins whose tuples repeat each key about 8 times: equal keys are first
+    summed in an LDS hash table and only the distinct keys are sorted (the
+    bin's distinct count comes from C's row pointers).  Also with the
+    2048-tuple tile."""
+    _say(f"heavy repeats {precision}")
+    a = random_sparse(3000, 60, 0.25, 51, "csc", values="signed")
+    b = random_sparse(60, 48, 0.4, 52, "csr", values="signed")
+    ref = oracle.spgemm(a, b)
+    assert ref["flop"] >= 4 * len(ref["colidx"])
+    for tune in (None, {"tile_tuples": 2048}, {"tile_tuples": 1024}):
+        _compare(_run(pb, a, b, precision, tune=tune), ref, precision)
