@@ -1141,13 +1141,13 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         rv[i] = gvb[p < N ? p : N - 1];  // in range for every lane (N >= 1); parked only for p < N
     }
-    // Bins whose keys repeat a lot (at most a quarter of the slots hold
+    // Bins whose keys repeat (at most half of the slots hold
     // distinct keys; that count is known from C's row pointers): equal keys
     // are first summed in an LDS hash table, in double, and only the
     // distinct keys, each with its sum, go on to the sort.
     {
         const int64_t D = bend - base;
-        if (D > 0 && 4 * D <= N && D <= TMAX / 4) {
+        if (D > 0 && 2 * D <= N && D <= TMAX / 4) {
             constexpr int TSD = TMAX / 2;  // table slots, load factor <= 1/2
             constexpr int LOG_TSD = (TSD >= 2048) ? 11 : (TSD >= 1024) ? 10 : 9;
             static_assert((1 << LOG_TSD) == TSD, "table size");

@@ -363,10 +363,10 @@ def test_sort_crowded_buckets(pb, run):
 
 @pytest.mark.parametrize("precision", ["f64", "f32c"])
 def test_sort_heavy_repeats(pb, precision):
-    """Bins whose tuples repeat each key about 8 times: equal keys are first
+    """Bins whose tuples repeat each key about 6 times: equal keys are first
     summed in an LDS hash table and only the distinct keys are sorted (the
-    bin's distinct count comes from C's row pointers).  Also with the
-    2048-tuple tile."""
+    path taken when at most half of a bin's slots hold distinct keys; the
+    count comes from C's row pointers).  Also with smaller tiles."""
     _say(f"heavy repeats {precision}")
     a = random_sparse(3000, 60, 0.25, 51, "csc", values="signed")
     b = random_sparse(60, 48, 0.4, 52, "csr", values="signed")
