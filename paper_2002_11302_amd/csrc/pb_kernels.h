@@ -169,10 +169,10 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
 // and a second pass writes one record per entry there (and the record's
 // place, per entry).  One workgroup per bucket adds each record's run slots
 // to its row's LDS counter; the fetched value, the run's offset inside the
-// row, goes back into the record.  A last pass over the entry ranges copies
-// each entry's offset from its record: the records of one range sit in one
-// short segment per bucket, so these reads, like every write, are whole
-// lines.  Same result as k_rowflop up to the order of the runs in a row.
+// row, is stored beside the record.  A last pass over the entry ranges
+// copies each entry's offset: the records of one range sit in one short
+// segment per bucket, so these reads, like every write, are whole lines.
+// Same result as k_rowflop up to the order of the runs in a row.
 constexpr int kRowBucketBits = 12;
 constexpr int kRowBucketRows = 1 << kRowBucketBits;
 constexpr int kMaxRowBuckets = 8192;      // LDS histogram of the distribution
@@ -192,8 +192,9 @@ struct RowBucketArgs {
                       // column holding the last entry
     uint32_t *hist;   // nbkt x ngrp counts (bucket-major), then their scan
     uint64_t *gflop;  // [ngrp]: multiplications of each workgroup's columns
-    uint2 *rec;       // bucket order: (row in bucket | slots << 12, column),
-                      // then (same, run offset in the row)
+    uint32_t *rec;    // bucket order: row in bucket | run slots << 12
+    uint32_t *roff;   // bucket order: the column when the slots field is
+                      // saturated, then the run's offset in its row
     uint32_t *posof;  // per entry: its record
     uint32_t *runpos;
     uint64_t *rowflop;
@@ -260,7 +261,8 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(RowBucketArgs a) {
     const int64_t nc = kend - k0 + 1;
     auto put = [&](int64_t e, int32_t r, uint32_t field, int64_t k) {
         const uint32_t pos = atomicAdd(&s_cur[r >> kRowBucketBits], 1u);
-        a.rec[pos] = make_uint2((uint32_t)(r & (kRowBucketRows - 1)) | field << kRowBucketBits, (uint32_t)k);
+        a.rec[pos] = (uint32_t)(r & (kRowBucketRows - 1)) | field << kRowBucketBits;
+        if (field == kRunField) a.roff[pos] = (uint32_t)k;
         a.posof[e] = pos;
     };
     if (nc <= kBucketCols) {
@@ -322,16 +324,19 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t
     const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
     constexpr int U = 4;
     for (int64_t p = (int64_t)p0 + threadIdx.x; p < p1; p += (int64_t)BLOCK * U) {
-        uint2 rc[U];
+        uint32_t rc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) rc[u] = a.rec[p + u * BLOCK < p1 ? p + u * BLOCK : p1 - 1];  // unconditional loads overlap
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (p + u * BLOCK >= p1) break;
-            uint64_t slots = rc[u].x >> kRowBucketBits;
-            if (slots == kRunField) slots = (uint64_t)run_slots(a.brp[rc[u].y + 1] - a.brp[rc[u].y], a.align);
-            const uint64_t old = atomicAdd(&s_cnt[rc[u].x & (kRowBucketRows - 1)], (unsigned long long)slots);
-            a.rec[p + u * BLOCK] = make_uint2(rc[u].x, (uint32_t)old);
+            uint64_t slots = rc[u] >> kRowBucketBits;
+            if (slots == kRunField) {
+                const uint32_t k = a.roff[p + u * BLOCK];
+                slots = (uint64_t)run_slots(a.brp[k + 1] - a.brp[k], a.align);
+            }
+            const uint64_t old = atomicAdd(&s_cnt[rc[u] & (kRowBucketRows - 1)], (unsigned long long)slots);
+            a.roff[p + u * BLOCK] = (uint32_t)old;
         }
     }
     __syncthreads();
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_offsets(RowBucketArgs a) {
         for (int u = 0; u < U; ++u) ps[u] = e + u * BLOCK < e1 ? a.posof[e + u * BLOCK] : 0u;
         uint32_t off[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) off[u] = a.rec[ps[u]].y;
+        for (int u = 0; u < U; ++u) off[u] = a.roff[ps[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (e + u * BLOCK < e1) a.runpos[e + u * BLOCK] = off[u];

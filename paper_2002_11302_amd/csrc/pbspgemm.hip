@@ -231,7 +231,7 @@ struct SymLayout {
     int32_t *kstart;
     uint32_t *hist;
     uint64_t *gflop;
-    uint2 *rec;
+    uint32_t *rec, *roff;
     uint32_t *posof;
     int nbkt, ngrp;
     int64_t epw, cpw;
@@ -299,7 +299,8 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
         L.kstart = cv.take<int32_t>(bs.ngrp + 1);
         L.hist = cv.take<uint32_t>(bs.nhist() + 1);
         L.gflop = cv.take<uint64_t>(bs.ngrp);
-        L.rec = cv.take<uint2>(nnza);
+        L.rec = cv.take<uint32_t>(nnza);
+        L.roff = cv.take<uint32_t>(nnza);
         L.posof = cv.take<uint32_t>(nnza);
     }
     if (count > 1) {
@@ -376,7 +377,8 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
                                   &L.tickets[0], &L.info->err, st, "flop scan"));
         if (p->rowcount == 2) {
             const RowBucketArgs ra{k,      p->nnzA, acp,      brp,    ari,     p->align, L.epw,    L.nbkt, L.ngrp,
-                                   L.cpw,  L.kstart, L.hist, L.gflop, L.rec,  L.posof,  L.runpos, L.R,    L.info};
+                                   L.cpw,  L.kstart, L.hist, L.gflop, L.rec,  L.roff,   L.posof,  L.runpos, L.R,
+                                   L.info};
             const int64_t nh = (int64_t)L.nbkt * L.ngrp;
             const size_t lds = (size_t)L.nbkt * sizeof(uint32_t);
             const dim3 grid((unsigned)L.ngrp), block(kBucketBlock);
