@@ -1436,15 +1436,29 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     }
     VT *cv = (VT *)cvals;
     if ((uint32_t)Nr - heads <= (uint32_t)Nr / 16) {
-        // few repeated keys: each head sums its (short) run itself
+        // few repeated keys: each head sums its (short) run itself.  The
+        // LDS reads of all of a thread's heads are issued together.
+        uint32_t hk[IPT], hs[IPT], hn[IPT];
+        VT hv[IPT];
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
+            const int pc = p < Nr ? p : Nr - 1;
+            hk[i] = keyA[pc];
+            hs[i] = slotA[pc];
+            hn[i] = p + 1 < Nr ? keyA[p + 1] : kSentinel;
+        }
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) hv[i] = vl[hs[i]];
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if (hr[i] != 0xffffffffu) {
                 const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-                const uint32_t key = keyA[p];
+                const uint32_t key = hk[i];
                 Merge<VT> mg;
-                mg.start(vl[slotA[p]]);
-                for (int q = p + 1; q < Nr && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
+                mg.start(hv[i]);
+                if (hn[i] == key)
+                    for (int q = p + 1; q < Nr && keyA[q] == key; ++q) mg.add(vl[slotA[q]]);
                 const int64_t out = base + wbase + hr[i];
                 if (out < capacity) {
                     const uint32_t vcol =
