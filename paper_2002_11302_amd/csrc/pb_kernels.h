@@ -495,15 +495,17 @@ __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64
 }
 
 // ---------------------------------------------------------------------------
-// Expand (Algorithm 2's outer-product loop).  The flop space [0, flop) is
-// cut into chunks of C = BLOCK*IPT tuples; tuple t lies in column k of A /
-// row k of B with F[k] <= t < F[k+1], and is the product of the i-th entry
-// of A(:,k) and the j-th entry of B(k,:), (i, j) = divmod(t - F[k], nnz(B(k,:))).
-// The tuples of one A entry e = (r, k) form a run that goes to row r's
-// range of the row-ordered tuple array, at offset runpos[e] (fixed by the
-// symbolic step), so bins are contiguous row ranges and no append needs an
-// atomic.  Consecutive lanes take consecutive tuples, so each run is written
-// by consecutive lanes to consecutive addresses.
+// Expand (Algorithm 2's outer-product loop).  The slot space [0, slots) is
+// cut into chunks of W slots, one wave each; slot t lies in column k of A /
+// row k of B with F[k] <= t < F[k+1] (F: scan of the columns' slots), and is
+// the product of the i-th entry of A(:,k) and the j-th entry of B(k,:),
+// (i, j) = divmod(t - F[k], run slots of B(k,:)); slots with j past
+// nnz(B(k,:)) are run padding and get the sentinel key.  The tuples of one
+// A entry e = (r, k) form a run that goes to row r's range of the
+// row-ordered tuple array, at offset runpos[e] (fixed by the symbolic step),
+// so bins are contiguous row ranges and no append needs an atomic.
+// Consecutive lanes take consecutive tuples, so each run is written by
+// consecutive lanes to consecutive addresses.
 struct ExpandArgs {
     int64_t flop, K;
     const int64_t *F;
@@ -968,12 +970,15 @@ struct SegRowPtrDst : NoSide {
 
 // ---------------------------------------------------------------------------
 // Sort + compress, one workgroup per bin.  The bin's N <= TMAX tuples (a
-// contiguous row range of the tuple array) are loaded once; keys are ordered
-// in LDS together with 16-bit slot numbers while the values wait in
-// registers; the values are then parked in LDS by slot.  Equal keys are
-// summed in sorted order by the first tuple of each run (Section 3.5's
-// merge) and written at their final place in C, whose row pointers the
-// count pass and the row scan have already produced.
+// contiguous row range of the tuple array) are loaded once, every load
+// issued before the first use; keys are ordered in LDS together with 16-bit
+// slot numbers while the values wait in registers; the values are then
+// parked in LDS by slot.  Equal keys are summed in sorted order by the first
+// tuple of each run (Section 3.5's merge) and written at their final place
+// in C, whose row pointers the count pass and the row scan have already
+// produced.  A bin in which at most half of the slots hold distinct keys
+// (the count is C's row-pointer difference) first sums equal keys in an LDS
+// hash table and sorts only the distinct keys.
 //
 // Ordering.  Keys are (row in bin) << cb | column.  The default path is a
 // one-pass bucket sort: bucket = (key - min) >> s with NB buckets, counted
