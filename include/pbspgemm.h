@@ -13,11 +13,13 @@
  *   expand    -- Algorithm 2's outer-product loop: every product
  *                A(r,k) * B(k,c) becomes a tuple appended to the bin of row r
  *                (Section 3.3);
- *   sort      -- per-bin radix sort on a packed 32-bit (row-in-bin, column)
- *                key (Section 3.4, "Preparing integer keys");
+ *   sort      -- per-bin sort in LDS on a packed 32-bit (row-in-bin, column)
+ *                key (Section 3.4): a bucket sort, or an LSD radix sort
+ *                when the keys cluster;
  *   compress  -- per-bin merge of equal keys by addition (Section 3.5);
- *   ConvertCSR-- row pointers and final positions from a scan over bins in
- *                row order (Algorithm 2, last step).
+ *   ConvertCSR-- entries per row from a key-only count pass, row pointers
+ *                from a scan over the rows, then every bin writes its rows
+ *                at their final places (Algorithm 2, last step).
  *
  * Conventions for every entry point
  *   - All matrix arrays are DEVICE pointers owned by the caller.  The library
@@ -60,7 +62,9 @@ typedef enum {
 typedef enum {
     PB_F64 = 0,  /* tuples and C values in double; sums in double */
     PB_F32C = 1  /* tuples carry fl32(a*b) (product in double, rounded once);
-                    each output is a compensated (Neumaier) float sum; C values float */
+                    each output is a compensated (Neumaier) float sum, or a
+                    double sum rounded once where a bin or column window is
+                    summed by accumulation; C values float */
 } pb_precision;
 
 /* A compressed sparse matrix.  For CSC, ptr has ncols+1 entries and idx
