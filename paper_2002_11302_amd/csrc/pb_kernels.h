@@ -1309,9 +1309,10 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
                 const uint32_t be = hist[bk];
                 const uint32_t bs = bk ? hist[bk - 1] : 0u;
                 uint32_t rank = bs;
-                for (uint32_t x = bs; x < be; ++x) {
-                    const uint32_t kx = keyB[x];
-                    rank += (kx < key) || (kx == key && x < (uint32_t)q);
+                for (uint32_t x = bs; x < be; x += 2) {
+                    const uint32_t k0 = keyB[x], k1 = keyB[x + 1];  // x + 1 stays inside the LDS arrays
+                    rank += (k0 < key) || (k0 == key && x < (uint32_t)q);
+                    if (x + 1 < be) rank += (k1 < key) || (k1 == key && x + 1 < (uint32_t)q);
                 }
                 keyA[rank] = key;
                 slotA[rank] = slotB[q];
