@@ -1157,16 +1157,14 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
     // distinct keys, each with its sum, go on to the sort.
     {
         const int64_t D = bend - base;
-        if (D > 0 && 2 * D <= N && D <= TMAX / 4) {
-            constexpr int TSD = TMAX / 2;  // table slots, load factor <= 1/2
-            constexpr int LOG_TSD = (TSD >= 2048) ? 11 : (TSD >= 1024) ? 10 : 9;
+        if (D > 0 && 2 * D <= N && D <= TMAX / 2) {
+            constexpr int TSD = TMAX;  // table slots, load factor <= 1/2
+            constexpr int LOG_TSD = (TSD >= 4096) ? 12 : (TSD >= 2048) ? 11 : (TSD >= 1024) ? 10 : 9;
             static_assert((1 << LOG_TSD) == TSD, "table size");
             static_assert(TSD % BLOCK == 0, "whole slots per thread");
-            uint32_t *tk = (uint32_t *)(smem + OFF_KA);                 // table keys
-            double *tv = (double *)(smem + OFF_KB);                     // table sums
-            uint32_t *ck = (uint32_t *)(smem + OFF_SA);                 // distinct keys
-            double *cs = (double *)(smem + OFF_KB + 4 * TMAX);          // their sums
-            static_assert(OFF_KB + 4 * TMAX + 8 * (TMAX / 4) <= OFF_END, "dedup arrays fit");
+            uint32_t *tk = (uint32_t *)(smem + OFF_KA);  // table keys
+            double *tv = (double *)(smem + OFF_KB);      // table sums
+            static_assert(OFF_KA + 4 * TSD <= OFF_KB && OFF_KB + 8 * TSD <= OFF_END, "table fits");
             for (int x = threadIdx.x; x < TSD; x += BLOCK) {
                 tk[x] = kSentinel;
                 tv[x] = 0.0;
@@ -1191,18 +1189,27 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
             }
             if (full) atomic_or_agent(a.err, (uint32_t)kErrTile);
             __syncthreads();
+            // compact the occupied slots to the front of the table, in
+            // place: every thread holds its slots in registers across the
+            // scan's barriers before any is overwritten
             constexpr int SPT = TSD / BLOCK;
+            uint32_t ck[SPT];
+            double cs[SPT];
             uint32_t occ = 0;
 #pragma unroll
-            for (int x = 0; x < SPT; ++x) occ += tk[threadIdx.x * SPT + x] != kSentinel;
+            for (int x = 0; x < SPT; ++x) {
+                ck[x] = tk[threadIdx.x * SPT + x];
+                cs[x] = tv[threadIdx.x * SPT + x];
+                occ += ck[x] != kSentinel;
+            }
             uint64_t tot;
             uint64_t at = block_excl_scan<BLOCK, SumOp>(occ, s_scan, tot);
+            __syncthreads();
 #pragma unroll
             for (int x = 0; x < SPT; ++x) {
-                const int sl = threadIdx.x * SPT + x;
-                if (tk[sl] != kSentinel) {
-                    ck[at] = tk[sl];
-                    cs[at] = tv[sl];
+                if (ck[x] != kSentinel) {
+                    tk[at] = ck[x];
+                    tv[at] = cs[x];
                     ++at;
                 }
             }
@@ -1211,8 +1218,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-                rk[i] = p < N ? ck[p] : kSentinel;
-                rv[i] = p < N ? (VT)cs[p] : (VT)0;
+                rk[i] = p < N ? tk[p] : kSentinel;
+                rv[i] = p < N ? (VT)tv[p] : (VT)0;
             }
             __syncthreads();  // the sort below reuses the LDS
         }

@@ -201,6 +201,7 @@ struct pb_plan {
     // budget, or that have rows wider than the tile)
     bool rounds_mode = false;
     int wbits = 0, lognwin = 0;
+    int64_t Tv = 0;  // tile of the virtual rows of wide rows (bins, and the dense accumulator above it)
     struct Round {
         int64_t r0 = 0, r1 = 0, b0 = 0, b1 = 0;  // rows and bins of the round
         int64_t slot0 = 0, flop = 0;              // first slot (R[r0]) and tuples
@@ -405,16 +406,17 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
                                   &L.tickets[1], &L.info->err, st, "row scan"));
         PB_TRY(launch_scan<BinOp>(
             m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count, -1},
-            BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2], &L.info->err, st,
-            "bin scan"));
+            BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2],
+            &L.info->err, st, "bin scan"));
     }
     return PB_OK;
 }
 
-// Sort + compress launch for `nbins` bins (the tile picks the kernel shape).
-pb_status launch_sort(const pb_plan *p, const SortArgs &sa, int64_t nbins, hipStream_t st) {
+// Sort + compress launch for `nbins` bins of at most T tuples (T picks the
+// kernel shape).
+pb_status launch_sort(const pb_plan *p, int64_t T, const SortArgs &sa, int64_t nbins, hipStream_t st) {
     const bool f64 = p->prec == PB_F64;
-    if (p->T <= kSortTmaxSmall) {
+    if (T <= kSortTmaxSmall) {
         if (f64)
             hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins),
                                dim3(kSortBlockSmall), 0, st, sa);
@@ -527,6 +529,16 @@ RoundLayout round_layout(void *base, const pb_plan *p, const pb_plan::Round &rd)
 // Cut the bins into rounds (consecutive bins, at most round_tuples tuples
 // each unless one bin alone is larger) and list every round's wide rows.
 // Reads the bin tables back once.
+// Tile of the virtual rows (a wide row's tuples in one column window).  Their
+// bins hold at most this many tuples and are sorted by the small sort kernel,
+// and a window with more tuples goes to the dense accumulator.  These windows
+// compress well (hub rows), and several smaller workgroups per CU sort them
+// faster than 4096-tuple bins, while 2048-tuple windows are still cheaper to
+// sort than to accumulate over 4096 columns.  Windows wider than the
+// accumulator keep the product's tile (a window above it is unsupported).
+constexpr int64_t kVirtualTile = 2048;
+int64_t virtual_tile(int64_t T, int wbits) { return wbits <= kDenseBits ? std::min(T, kVirtualTile) : T; }
+
 pb_status build_rounds(pb_plan *p, hipStream_t st) {
     const int64_t nbins = (int64_t)p->h.nbins;
     std::vector<int32_t> brow(nbins + 1);
@@ -537,6 +549,7 @@ pb_status build_rounds(pb_plan *p, hipStream_t st) {
     p->rounds_mode = true;
     p->lognwin = std::max(0, std::min(kMaxLogWin, p->cb - kDenseBits));
     p->wbits = p->cb - p->lognwin;
+    p->Tv = virtual_tile(p->T, p->wbits);
     const int64_t budget = p->round_tuples > 0 ? p->round_tuples : INT64_MAX;
     const int64_t T = p->T;
     const int64_t vmax = (int64_t)1 << 30;  // virtual rows per round (32-bit bin tables)
@@ -597,11 +610,11 @@ pb_status build_rounds(pb_plan *p, hipStream_t st) {
             rd.nchunks = cpre[rd.nbig];
             rd.nvirt = rd.nbig << p->lognwin;
             // virtual bins: every bin but the segment and oversize starts spans at
-            // least T/2 of weight (tuples + rows); oversize rows have > T tuples
-            // (floor(weight / H) changes: weight <= tuples + 2 per row, H >= T/2;
-            // rows over T/2 start a bin and make their successor start one)
-            const int64_t over = rd.bigflop / (T + 1) + 1;
-            const int64_t bound = (6 * rd.bigflop + 4 * rd.nvirt) / T + rd.nbig + 4;
+            // least Tv/2 of weight (tuples + rows); oversize rows have > Tv tuples
+            // (floor(weight / H) changes: weight <= tuples + 2 per row, H >= Tv/2;
+            // rows over Tv/2 start a bin and make their successor start one)
+            const int64_t over = rd.bigflop / (p->Tv + 1) + 1;
+            const int64_t bound = (6 * rd.bigflop + 4 * rd.nvirt) / p->Tv + rd.nbig + 4;
             rd.nvbins = std::min(rd.nvirt, bound);
             rd.ndense = std::min(rd.nvirt, over);
         }
@@ -674,11 +687,11 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         ProfScope ps(st, 4);
         hipLaunchKernelGGL(k_big_hist<512>, dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
         PB_LAUNCHED("wide-row histogram");
-        PB_TRY(launch_scan<SumOp>(rd.nvirt, U32Src{L.cnt_v}, RowFlopDst{L.Rv, rd.nvirt, (uint64_t)(p->T / 2), L.vinfo},
+        PB_TRY(launch_scan<SumOp>(rd.nvirt, U32Src{L.cnt_v}, RowFlopDst{L.Rv, rd.nvirt, (uint64_t)(p->Tv / 2), L.vinfo},
                                   L.st_v, &L.tickets[2], L.err, st, "virtual row scan"));
         PB_TRY(launch_scan<BinOp>(rd.nvirt,
-                                  BinSrc{L.Rv, L.vinfo, (uint64_t)p->T, 32 - p->wbits, nullptr, 0, p->lognwin},
-                                  BinDst{L.vrowtab, L.vbinrow0, L.vbinoff, L.Rv, rd.nvirt, (uint64_t)p->T, L.vinfo,
+                                  BinSrc{L.Rv, L.vinfo, (uint64_t)p->Tv, 32 - p->wbits, nullptr, 0, p->lognwin},
+                                  BinDst{L.vrowtab, L.vbinrow0, L.vbinoff, L.Rv, rd.nvirt, (uint64_t)p->Tv, L.vinfo,
                                          L.dense},
                                   L.st_vb, &L.tickets[3], L.err, st, "virtual bin scan"));
         if (f64) hipLaunchKernelGGL((k_big_scatter<512, double>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
@@ -701,8 +714,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
             PB_LAUNCHED("row counts");
         }
         if (rd.nbig) {
-            CountArgs cv{L.vbinrow0, L.vbinoff, L.keys2, p->wbits, L.rownnz_v, L.err, p->T, 0, 0, 0, &L.vinfo->nbins};
-            if (p->T <= kSortTmaxSmall)
+            CountArgs cv{L.vbinrow0, L.vbinoff, L.keys2, p->wbits, L.rownnz_v, L.err, p->Tv, 0, 0, 0, &L.vinfo->nbins};
+            if (p->Tv <= kSortTmaxSmall)
                 hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)rd.nvbins),
                                    dim3(kCountBlock), 0, st, cv);
             else
@@ -730,12 +743,12 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         if (nb > 0) {
             SortArgs sa{p->binrow0, p->binoff, L.keys, L.vals, p->cb, L.err, rowptr_out, colidx, cval, capacity,
                         nullptr, nullptr, 1, p->T, rd.b0, rd.slot0, rd.r0, nullptr, 0, 0};
-            PB_TRY(launch_sort(p, sa, nb, st));
+            PB_TRY(launch_sort(p, p->T, sa, nb, st));
         }
         if (rd.nbig) {
             SortArgs sv{L.vbinrow0, L.vbinoff, L.keys2, L.vals2, p->wbits, L.err, L.rowptr_v, colidx, cval, capacity,
-                        nullptr, nullptr, 1, p->T, 0, 0, 0, &L.vinfo->nbins, p->wbits, (uint32_t)(nwin - 1)};
-            PB_TRY(launch_sort(p, sv, rd.nvbins, st));
+                        nullptr, nullptr, 1, p->Tv, 0, 0, 0, &L.vinfo->nbins, p->wbits, (uint32_t)(nwin - 1)};
+            PB_TRY(launch_sort(p, p->Tv, sv, rd.nvbins, st));
             if (f64) hipLaunchKernelGGL((k_dense<512, double, true>), dim3(dgrid), dim3(512), 0, st, da);
             else hipLaunchKernelGGL((k_dense<512, float, true>), dim3(dgrid), dim3(512), 0, st, da);
             PB_LAUNCHED("dense output");
