@@ -91,6 +91,30 @@ __device__ __forceinline__ void big_chunk_range(const BigArgs &a, int64_t c, int
     e = s + kBigChunk < end ? s + kBigChunk : end;
 }
 
+// A wave's lanes hold consecutive tuples of a wide row, and a run's columns
+// ascend, so neighbouring lanes often fall in the same window.  Lanes are
+// grouped into segments of neighbours with the same window (lanes with no
+// tuple carry kNoWin and form segments of their own); the head (first lane)
+// of each segment does one LDS update for the whole segment.
+constexpr uint32_t kNoWin = 0xffffffffu;
+struct WinSegment {
+    uint32_t head;  // first lane of this lane's segment
+    uint32_t len;   // lanes in the segment (meaningful at the head)
+    bool is_head;
+};
+__device__ __forceinline__ WinSegment win_segment(uint32_t win) {
+    const uint32_t lane = lane_id();
+    const uint32_t prev = __shfl_up(win, 1u, kWave);
+    const uint64_t heads = ballot(lane == 0 || prev != win);
+    const uint64_t upto = heads & ((2ull << lane) - 1ull);  // heads at or below this lane (lane 63: all)
+    const uint64_t above = heads & ~((2ull << lane) - 1ull);
+    WinSegment g;
+    g.head = 63u - (uint32_t)__builtin_clzll(upto);
+    g.is_head = g.head == lane;
+    g.len = (above ? (uint32_t)__builtin_ctzll(above) : (uint32_t)kWave) - lane;
+    return g;
+}
+
 // Tuples per window, per chunk (kept for the scatter) and per virtual row.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_big_hist(BigArgs a) {
@@ -111,8 +135,11 @@ __global__ __launch_bounds__(BLOCK) void k_big_hist(BigArgs a) {
             kk[v] = p < e ? a.keys[p] : kSentinel;
         }
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-            if (kk[v] != kSentinel) atomicAdd(&h[(kk[v] & colmask) >> a.wbits], 1u);
+        for (int v = 0; v < V; ++v) {
+            const uint32_t win = kk[v] != kSentinel ? (kk[v] & colmask) >> a.wbits : kNoWin;
+            const WinSegment g = win_segment(win);
+            if (g.is_head && win != kNoWin) atomicAdd(&h[win], g.len);
+        }
     }
     __syncthreads();
     uint32_t *ch = a.chist + (int64_t)blockIdx.x * nwin;
@@ -184,8 +211,13 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
             col[u] &= colmask;
         }
 #pragma unroll
-        for (int u = 0; u < PER; ++u)
-            if (real[u]) rank[u] = atomicAdd(&hsc[col[u] >> a.wbits], 1u);
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t win = real[u] ? col[u] >> a.wbits : kNoWin;
+            const WinSegment g = win_segment(win);
+            uint32_t base = 0;
+            if (g.is_head && win != kNoWin) base = atomicAdd(&hsc[win], g.len);
+            rank[u] = (uint32_t)__shfl((int)base, (int)g.head, kWave) + (lane_id() - g.head);
+        }
         __syncthreads();
         // exclusive scan of the step's window counts
         uint32_t cnt[WPT];
