@@ -53,7 +53,7 @@ pb_status fail(pb_status s, const char *fmt, ...) {
 constexpr int kScanBlock = 256, kScanIpt = 8, kScanTile = kScanBlock * kScanIpt;
 constexpr int kSortBlock = 512, kSortTmax = 4096;
 constexpr int kSortBlockSmall = 256, kSortTmaxSmall = 2048;
-constexpr int kCountBlock = 512;
+constexpr int kCountBlock = 512, kCountBlockSmall = 256;
 constexpr int kDefaultTile = 4096;
 constexpr int kDefaultChunk = 1024;
 
@@ -706,8 +706,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         if (nb > 0) {
             CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err, p->T, rd.b0, rd.slot0, rd.r0, nullptr};
             if (p->T <= kSortTmaxSmall)
-                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)nb), dim3(kCountBlock), 0,
-                                   st, ca);
+                hipLaunchKernelGGL((k_row_nnz<kCountBlockSmall, kSortTmaxSmall>), dim3((unsigned)nb),
+                                   dim3(kCountBlockSmall), 0, st, ca);
             else
                 hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmax>), dim3((unsigned)nb), dim3(kCountBlock), 0, st,
                                    ca);
@@ -716,8 +716,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         if (rd.nbig) {
             CountArgs cv{L.vbinrow0, L.vbinoff, L.keys2, p->wbits, L.rownnz_v, L.err, p->Tv, 0, 0, 0, &L.vinfo->nbins};
             if (p->Tv <= kSortTmaxSmall)
-                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)rd.nvbins),
-                                   dim3(kCountBlock), 0, st, cv);
+                hipLaunchKernelGGL((k_row_nnz<kCountBlockSmall, kSortTmaxSmall>), dim3((unsigned)rd.nvbins),
+                                   dim3(kCountBlockSmall), 0, st, cv);
             else
                 hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmax>), dim3((unsigned)rd.nvbins), dim3(kCountBlock),
                                    0, st, cv);
@@ -817,8 +817,8 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
             ProfScope ps(st, 3);
             CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err, p->T, 0, 0, 0, nullptr};
             if (p->T <= kSortTmaxSmall)
-                hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmaxSmall>), dim3((unsigned)nbins), dim3(kCountBlock), 0,
-                                   st, ca);
+                hipLaunchKernelGGL((k_row_nnz<kCountBlockSmall, kSortTmaxSmall>), dim3((unsigned)nbins),
+                                   dim3(kCountBlockSmall), 0, st, ca);
             else
                 hipLaunchKernelGGL((k_row_nnz<kCountBlock, kSortTmax>), dim3((unsigned)nbins), dim3(kCountBlock), 0, st,
                                    ca);
