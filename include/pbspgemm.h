@@ -88,7 +88,8 @@ typedef struct {
 } pb_csr_out;
 
 /* Tuning knobs; 0 selects the default.
- *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096
+ *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096;
+ *                 default 2048 for a single product, 4096 for a batch
  *   expand_chunk  tuples per expand wave: 256, 512, 1024 or 2048
  *   round_tuples  upper bound on tuple slots per round (0 = no bound): the
  *                 rows of C are cut into rounds of consecutive bins so that

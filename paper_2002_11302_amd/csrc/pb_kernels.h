@@ -1070,7 +1070,7 @@ __device__ __forceinline__ Merge<float> shfl_up_merge(const Merge<float> &x, int
 constexpr uint32_t kBucketLimit = 40;
 
 template <int BLOCK, int TMAX, class VT>
-__global__ __launch_bounds__(BLOCK) void k_sort_compress(SortArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2048 ? 5 : 1))) void k_sort_compress(SortArgs a) {
     constexpr int NW = BLOCK / kWave;
     constexpr int IPT = TMAX / BLOCK;
     constexpr int NB = TMAX >= 4096 ? TMAX : TMAX / 2;  // buckets of the one-pass path

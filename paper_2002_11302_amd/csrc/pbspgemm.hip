@@ -54,7 +54,10 @@ constexpr int kScanBlock = 256, kScanIpt = 8, kScanTile = kScanBlock * kScanIpt;
 constexpr int kSortBlock = 512, kSortTmax = 4096;
 constexpr int kSortBlockSmall = 256, kSortTmaxSmall = 2048;
 constexpr int kCountBlock = 512, kCountBlockSmall = 256;
-constexpr int kDefaultTile = 4096;
+// Default tiles: 2048-tuple bins for a single product (the small sort kernel
+// keeps five workgroups per CU); 4096 for a batch, whose rows must each fit
+// one bin.
+constexpr int kDefaultTile = 2048, kDefaultTileBatched = 4096;
 constexpr int kDefaultChunk = 1024;
 
 constexpr int64_t kMaxDim = (1ll << 31) - 1;
@@ -135,8 +138,9 @@ int col_bits(int64_t n) {
     return 64 - __builtin_clzll((uint64_t)(n - 1));
 }
 
-pb_status resolve_tune(const pb_tune *t, int *T, int *chunk, int64_t *round_tuples, int *align, int *rowcount) {
-    *T = kDefaultTile;
+pb_status resolve_tune(const pb_tune *t, int default_tile, int *T, int *chunk, int64_t *round_tuples, int *align,
+                       int *rowcount) {
+    *T = default_tile;
     *chunk = kDefaultChunk;
     *round_tuples = 0;
     *align = 0;
@@ -997,7 +1001,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
     int T, chunk, align, rowreq;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align, &rowreq));
+    PB_TRY(resolve_tune(tune, kDefaultTile, &T, &chunk, &round_tuples, &align, &rowreq));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
     const int rowcount = pick_rowcount(rowreq, m, k, A->nnz);
     if (rowcount < 0)
@@ -1180,7 +1184,7 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
     int T, chunk, align, rowreq;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, &T, &chunk, &round_tuples, &align, &rowreq));
+    PB_TRY(resolve_tune(tune, kDefaultTileBatched, &T, &chunk, &round_tuples, &align, &rowreq));
     std::vector<ProbDesc> hd;
     int64_t m, k, n, nnza, nnzb;
     batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);
