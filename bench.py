@@ -561,6 +561,28 @@ def summarize_profiles(src: str, out_dir: str, command: str, pmc_command: str) -
         f.write("\n")
 
 
+def summarize_trace(src: str, out_path: str, title: str, command: str, per=lambda name: 1) -> None:
+    """Write a rocprofv3 kernel-trace stats summary (the kernels of src's
+    kernel_stats.csv, longest first, with the time per product when the
+    traced run did per(kernel name) products with that kernel)."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(src, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no kernel_stats.csv under {src}")
+    with open(files[0]) as f:
+        stats = sorted(csv.DictReader(f), key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel-trace summary: {title}", f"# command: {command}",
+             f"# {'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'ms_per_product':>14s} {'pct':>6s}"]
+    for r in stats:
+        tot = float(r["TotalDurationNs"]) / 1e6
+        lines.append(f"  {r['Name'][:70]:70s} {r['Calls']:>6s} {float(r['AverageNs']) / 1e3:10.2f} {tot:10.3f} "
+                     f"{tot / per(r['Name']):14.3f} {float(r['Percentage']):6.2f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -578,9 +600,22 @@ def main():
                          "sampled-row parity and the autotuner's choice per point")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     ap.add_argument("--profile-command", default="", help="the kernel-trace command, recorded in the summaries")
+    ap.add_argument("--summarize-rmat-trace", metavar="DIR",
+                    help="write profiles/kernels_rmat_s20_ef16.txt from a rocprofv3 kernel trace of "
+                         "`bench.py --rmat --steps 2 --warmup 1 --no-cpu-baseline` in DIR")
     ap.add_argument("--pmc-command", default="",
                     help="the counter command, with {COUNTER} and {KIND} for FETCH_SIZE/fetch and WRITE_SIZE/write")
     args = ap.parse_args()
+    if args.summarize_rmat_trace:
+        # that run does, per precision, one product to count nnz(C), one
+        # warm-up and two timed products: kernels templated on the value
+        # type ran in 4 products, the others in 8 (the ER n=2^20 steps that
+        # run first are a few ms against seconds)
+        summarize_trace(args.summarize_rmat_trace, os.path.join(ROOT, "profiles", "kernels_rmat_s20_ef16.txt"),
+                        "R-MAT scale 20 ef 16 C = A*A, FP64 and FP32c, 4 products each (plus the ER n=2^20 d=16 "
+                        "steps bench.py runs first)", args.profile_command,
+                        per=lambda name: 4 if ("double" in name or "float" in name) else 8)
+        return
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command,
                            args.pmc_command)
