@@ -158,11 +158,12 @@ pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision
 /*
  * Rows wider than the tile.  A row of C whose tuples exceed tile_tuples is
  * split after the expand into windows of consecutive columns (2^12 columns
- * while n <= 2^22); every window is sorted and compressed like a row, or, when
- * it alone exceeds the tile, summed in LDS by a dense accumulator (tuples
- * added in double; FP32C rounds the double sum to float).  A window that
- * exceeds the tile while being wider than 2^12 columns (n > 2^22 and heavily
- * clustered columns) makes the numeric step return PB_ERR_UNSUPPORTED.
+ * while n <= 2^22); windows are binned and sorted and compressed like rows,
+ * in bins of at most min(tile_tuples, 2048) tuples, and a window with more
+ * tuples than that is summed in LDS by a dense accumulator (tuples added in
+ * double; FP32C rounds the double sum to float).  A window that exceeds the
+ * tile while being wider than 2^12 columns (n > 2^22 and heavily clustered
+ * columns) makes the numeric step return PB_ERR_UNSUPPORTED.
  *
  * Numeric step (Algorithm 2: expand into bins, sort and compress each bin,
  * ConvertCSR).  A_csc / B_csr must be the matrices given to the symbolic

@@ -13,10 +13,11 @@
 // arbitrary column order.  They are partitioned by column window
 // (2^wbits consecutive columns) into a second buffer.  Each (row, window)
 // pair is a virtual row; virtual rows are cut into bins exactly like rows
-// (a bin never spans two wide rows) and sorted and compressed by the same
-// kernels, with key = (virtual row in bin) << wbits | column in window.  A
-// virtual row that alone exceeds T is summed in LDS by a dense accumulator
-// over its 2^wbits columns instead of being sorted.
+// (a bin never spans two wide rows), with their own tile (at most 2048
+// tuples), and sorted and compressed by the same kernels, with key =
+// (virtual row in bin) << wbits | column in window.  A virtual row that
+// alone exceeds that tile is summed in LDS by a dense accumulator over its
+// 2^wbits columns instead of being sorted.
 #pragma once
 #include "pb_kernels.h"
 
@@ -300,8 +301,8 @@ __global__ __launch_bounds__(256) void k_big_rowptr(int64_t nbig, int lognwin, c
 }
 
 // ---- wide rows: dense accumulation of one window ---------------------------
-// For a virtual row with more tuples than the tile: a bitmap of the window's
-// columns marks every position hit (so cancelled sums stay stored), and
+// For a virtual row with more tuples than the virtual tile: a bitmap of the
+// window's columns marks every position hit (so cancelled sums stay stored), and
 // (OUT) a double accumulator per column receives every tuple by an LDS
 // atomic add.  Count mode writes the number of marked columns; output mode
 // writes the marked columns in order at the virtual row's place in C.
