@@ -326,9 +326,10 @@ template <int BLOCK, class VT, bool OUT>
 __global__ __launch_bounds__(BLOCK) void k_dense(DenseArgs a) {
     constexpr int WD = 1 << kDenseBits;
     constexpr int CPT = WD / BLOCK;  // columns per thread
-    static_assert(CPT == 8, "one bitmap byte per thread");
+    static_assert(CPT == 8, "two flag words per thread");
     __shared__ double acc[OUT ? WD : 1];
-    __shared__ uint32_t bits[WD / 32];
+    __shared__ uint32_t hitw[WD / 4];  // one flag byte per column: 1 when some tuple hits it
+    uint8_t *hit = (uint8_t *)hitw;
     __shared__ uint64_t s_scan[BLOCK / kWave + 1];
     if (a.wbits > kDenseBits) {
         if (threadIdx.x == 0 && *a.count > 0) atomic_or_agent(a.err, (uint32_t)kErrWide);
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense(DenseArgs a) {
     for (int64_t it = blockIdx.x; it < cnt; it += gridDim.x) {
         const int64_t v = a.list[it];
         const int64_t s = (int64_t)a.Rv[v], e = (int64_t)a.Rv[v + 1];
-        for (int x = threadIdx.x; x < WD / 32; x += BLOCK) bits[x] = 0;
+        for (int x = threadIdx.x; x < WD / 4; x += BLOCK) hitw[x] = 0;
         if (OUT)
             for (int x = threadIdx.x; x < ncol; x += BLOCK) acc[x] = 0.0;
         __syncthreads();
@@ -357,18 +358,23 @@ __global__ __launch_bounds__(BLOCK) void k_dense(DenseArgs a) {
                 if (OUT) vv[u] = gv[q];
             }
             // lanes past the end repeat the last tuple with nothing to add
-            // (its column's bit is set by its own lane), so every use of
-            // the loads is unconditional and they stay overlapped
+            // (its column is hit anyway), so every use of the loads is
+            // unconditional and they stay overlapped; the flags are plain
+            // byte stores (every writer stores 1)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool in = p0 + u * BLOCK < e;
                 const uint32_t c = kc[u] & wmask;
-                atomicOr(&bits[c >> 5], in ? 1u << (c & 31) : 0u);
+                hit[c] = 1;
                 if (OUT) atomicAdd(&acc[c], in ? (double)vv[u] : 0.0);
             }
         }
         __syncthreads();
-        const uint32_t byte = (bits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 8)) & 0xffu;
+        // this thread's 8 columns as a bit mask
+        const uint64_t f8 = ((uint64_t)hitw[2 * threadIdx.x + 1] << 32) | hitw[2 * threadIdx.x];
+        uint32_t byte = 0;
+#pragma unroll
+        for (int x = 0; x < CPT; ++x) byte |= (uint32_t)((f8 >> (8 * x)) & 1u) << x;
         const uint32_t mine = (uint32_t)__builtin_popcount(byte);
         uint64_t total;
         const uint64_t ex = block_excl_scan<BLOCK, SumOp>(mine, s_scan, total);
