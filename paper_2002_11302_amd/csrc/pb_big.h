@@ -24,7 +24,7 @@
 namespace pb {
 
 constexpr int kBigChunk = 65536;  // tuples of a wide row per partition workgroup
-constexpr int kBigSub = 2048;     // tuples staged in LDS per partition step
+constexpr int kBigSub = 4096;     // tuples staged in LDS per partition step (two workgroups per CU)
 constexpr int kMaxLogWin = 10;    // at most 1024 windows per wide row
 constexpr int kDenseBits = 12;    // dense accumulator: 4096 columns
 
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
     constexpr int PER = kBigSub / BLOCK;
     constexpr int WPT = NWMAX / BLOCK;
     static_assert(kBigSub % BLOCK == 0 && NWMAX % BLOCK == 0, "shape");
-    __shared__ int64_t cbase[NWMAX];
+    __shared__ uint32_t cbase[NWMAX];  // per window: first slot, relative to the row's first virtual row
     __shared__ uint32_t rlw[NWMAX];
     __shared__ uint32_t run[NWMAX];
     __shared__ uint32_t hsc[NWMAX];
@@ -172,6 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
     const int nwin = 1 << a.lognwin;
     int64_t i, s, e;
     big_chunk_range(a, blockIdx.x, i, s, e);
+    const int64_t vbase = (int64_t)a.Rv[i << a.lognwin];  // the row's tuples: fewer than 2^32 after it
     const uint32_t *ch = a.chist + (int64_t)blockIdx.x * nwin;
     for (int x = threadIdx.x; x < nwin; x += BLOCK) {
         const uint32_t c = ch[x];
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
         if (c) {
             const int64_t v = (i << a.lognwin) + x;
             const uint32_t off = atomic_add_agent(&a.cur_v[v], c);
-            cbase[x] = (int64_t)a.Rv[v] + off;
+            cbase[x] = (uint32_t)((int64_t)a.Rv[v] - vbase) + off;
             rlw[x] = a.vrowtab[v].rl << a.wbits;
         }
     }
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
         __syncthreads();
         for (int q = threadIdx.x; q < nput; q += BLOCK) {
             const uint32_t w = swin[q];
-            const int64_t dest = cbase[w] + run[w] + (q - (int)hoff[w]);
+            const int64_t dest = vbase + (int64_t)cbase[w] + run[w] + (q - (int)hoff[w]);
             if ((uint64_t)dest < (uint64_t)a.nbigflop) {
                 a.keys2[dest] = skey[q];
                 ov[dest] = sval[q];
