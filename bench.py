@@ -666,7 +666,18 @@ def main():
         "phases_ms": {k: round(v, 5) for k, v in phase_ms.items()},
         "model_bytes": mb,
         "whole_path_model_GBps": round(mb["total"] / sec / 1e9, 1),
+        "paper_MFLOPS": round(flop / sec / 1e6, 1),  # the paper's unit: multiplications per second
+        "phase_model_GBps": {k: round(mb[k] / (phase_ms[k] * 1e-3) / 1e9, 1) for k in ("expand", "sort_compress")},
     }
+    amp = {}
+    for k in ("expand", "sort_compress"):
+        t = traffic_for(f"k_{k}<{args.precision}>")
+        if t:
+            amp[k] = round(t / mb[k], 3)
+    out["traffic_over_model"] = amp or None
+    beta = copy_bandwidth(pb, torch)
+    out["copy_GBps"] = round(beta, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / beta, 4)
     if args.extras:
         log("extras: FP32c step and copy bandwidth")
         other = "f32c" if args.precision == "f64" else "f64"
@@ -676,7 +687,7 @@ def main():
             f"{other}_GFLOPS": round(2.0 * flop / sec2 / 1e9, 3),
             f"{other}_ms_per_step": round(sec2 * 1e3, 4),
             f"{other}_phases_ms": {k: round(ms / max(n, 1), 5) for k, (ms, n) in prof2.items()},
-            "copy_GBps": round(copy_bandwidth(pb, torch), 1),
+            "copy_GBps": out["copy_GBps"],
         }
         out["extras"][f"{other}_speedup_vs_{args.precision}"] = round(sec / sec2, 3)
         if other == "f32c":
@@ -691,7 +702,7 @@ def main():
         import tempfile
 
         ex = out.setdefault("extras", {})
-        beta = ex.get("copy_GBps") or round(copy_bandwidth(pb, torch), 1)
+        beta = out["copy_GBps"]
         ex["sweep_copy_GBps"] = beta
         ex["sweep"] = bench_sweep(pb, torch, beta, os.path.join(tempfile.mkdtemp(), "autotune.json"))
     if not args.no_cpu_baseline:
