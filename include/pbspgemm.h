@@ -156,6 +156,17 @@ pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision
                           size_t *workspace_bytes);
 
 /*
+ * Operand content.  The kernels trust the operands to be well formed: ptr[0]
+ * = 0, ptr non-decreasing, ptr[major] = nnz, indices inside the matrix and
+ * strictly increasing within each column (A) or row (B); a malformed operand
+ * can make them read or write out of bounds.  With PB_VALIDATE=1 in the
+ * environment, spgemm_symbolic and spgemm_batched_symbolic copy every
+ * operand's ptr and idx arrays to the host (stream-ordered) and check them
+ * before any launch, returning PB_ERR_ARG with the first violation in
+ * spgemm_last_error().
+ */
+
+/*
  * Rows wider than the tile.  A row of C whose tuples exceed tile_tuples is
  * split after the expand into windows of consecutive columns (2^12 columns
  * while n <= 2^22); windows are binned and sorted and compressed like rows,

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -130,6 +131,44 @@ pb_status check_csx(const pb_csx *x, const char *name) {
     if (x->nnz > kMaxCount) return fail(PB_ERR_RANGE, "%s nnz exceeds 2^62", name);
     if (!x->ptr) return fail(PB_ERR_ARG, "%s.ptr is NULL", name);
     if (x->nnz > 0 && (!x->idx || !x->val)) return fail(PB_ERR_ARG, "%s.idx/val is NULL with nnz > 0", name);
+    return PB_OK;
+}
+
+// Content check of an operand, on when PB_VALIDATE=1 is in the environment
+// (a debugging aid; the kernels otherwise trust the inputs): ptr[0] = 0,
+// ptr non-decreasing, ptr[major] = nnz, every index in [0, minor) and
+// strictly increasing inside its line.  The arrays are copied to the host
+// (stream-ordered), so no kernel ever runs on an operand that fails.
+bool validate_enabled() {
+    const char *v = getenv("PB_VALIDATE");
+    return v && v[0] == '1';
+}
+
+pb_status validate_csx(const pb_csx *x, const char *name, bool csc, hipStream_t st) {
+    const int64_t major = csc ? x->ncols : x->nrows, minor = csc ? x->nrows : x->ncols;
+    std::vector<int64_t> ptr((size_t)major + 1);
+    std::vector<int32_t> idx((size_t)x->nnz);
+    PB_HIP(hipMemcpyAsync(ptr.data(), x->ptr, sizeof(int64_t) * ptr.size(), hipMemcpyDeviceToHost, st));
+    if (x->nnz) PB_HIP(hipMemcpyAsync(idx.data(), x->idx, sizeof(int32_t) * idx.size(), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    const char *line = csc ? "column" : "row";
+    if (ptr[0] != 0) return fail(PB_ERR_ARG, "%s: ptr[0] is %lld, not 0", name, (long long)ptr[0]);
+    if (ptr[(size_t)major] != x->nnz)
+        return fail(PB_ERR_ARG, "%s: ptr[%lld] is %lld, not nnz = %lld", name, (long long)major,
+                    (long long)ptr[(size_t)major], (long long)x->nnz);
+    for (int64_t j = 0; j < major; ++j) {
+        const int64_t s = ptr[(size_t)j], e = ptr[(size_t)j + 1];
+        if (e < s) return fail(PB_ERR_ARG, "%s: ptr decreases at %s %lld", name, line, (long long)j);
+        if (e > x->nnz) return fail(PB_ERR_ARG, "%s: ptr exceeds nnz at %s %lld", name, line, (long long)j);
+        for (int64_t q = s; q < e; ++q) {
+            const int32_t v = idx[(size_t)q];
+            if (v < 0 || v >= minor)
+                return fail(PB_ERR_ARG, "%s: index %d out of [0, %lld) in %s %lld", name, v, (long long)minor, line,
+                            (long long)j);
+            if (q > s && v <= idx[(size_t)q - 1])
+                return fail(PB_ERR_ARG, "%s: indices not strictly increasing in %s %lld", name, line, (long long)j);
+        }
+    }
     return PB_OK;
 }
 
@@ -1019,6 +1058,10 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     if (cb > 31) return fail(PB_ERR_RANGE, "n too large for packed keys");
 
     hipStream_t st = (hipStream_t)hip_stream;
+    if (validate_enabled()) {
+        PB_TRY(validate_csx(A, "A", true, st));
+        PB_TRY(validate_csx(B, "B", false, st));
+    }
     SymLayout L = sym_layout(sym_ws, m, k, A->nnz, B->nnz, 1, rowcount);
     pb_plan *p = new pb_plan();
     p->rowcount = rowcount;
@@ -1206,6 +1249,15 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     if (nnzb >= (int64_t)1 << 32) return fail(PB_ERR_RANGE, "nnz(B) must be below 2^32 (32-bit in-row run offsets)");
     const int cb = col_bits(n);
     if (cb > 31) return fail(PB_ERR_RANGE, "n too large for packed keys");
+    if (validate_enabled()) {
+        for (int32_t i = 0; i < count; ++i) {
+            char na[32], nb[32];
+            snprintf(na, sizeof na, "A[%d]", i);
+            snprintf(nb, sizeof nb, "B[%d]", i);
+            PB_TRY(validate_csx(&A[i], na, true, (hipStream_t)hip_stream));
+            PB_TRY(validate_csx(&B[i], nb, false, (hipStream_t)hip_stream));
+        }
+    }
     if (count == 1) {
         ProbDesc e{};
         e.mbase = hd[0].m;
