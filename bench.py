@@ -37,7 +37,7 @@ def log(msg: str) -> None:
 
 def model_bytes(m, k, nnz_a, nnz_b, flop, nnz_c, precision: str) -> dict:
     """Algorithmic bytes per phase (traffic model of the paper's Table 3 with
-    this build's widths: int64 pointers, int32 indices, double inputs, packed
+    this library's widths: int64 pointers, int32 indices, double inputs, packed
     32-bit keys; tuple = key + value, C entry = column + value)."""
     bt = 12 if precision == "f64" else 8
     bc = 12 if precision == "f64" else 8

@@ -55,7 +55,7 @@ typedef enum {
     PB_ERR_WORKSPACE = 4,   /* workspace pointer null or smaller than reported */
     PB_ERR_CAPACITY = 5,    /* C.capacity < nnz(C); *nnzC receives the size needed */
     PB_ERR_HIP = 6,         /* a HIP runtime call failed (detail in spgemm_last_error) */
-    PB_ERR_UNSUPPORTED = 7, /* a case this build does not handle (detail in spgemm_last_error) */
+    PB_ERR_UNSUPPORTED = 7, /* a case the library does not handle (detail in spgemm_last_error) */
     PB_ERR_INTERNAL = 8     /* a device-side consistency check failed */
 } pb_status;
 
