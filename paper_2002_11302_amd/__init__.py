@@ -18,7 +18,8 @@ __all__ = [
     "DeviceCsx", "DeviceCsr", "Plan", "PbError", "PHASES",
     "spgemm_symbolic", "spgemm_numeric", "spgemm_plan_info", "spgemm_plan_destroy",
     "spgemm_status_string", "spgemm_last_error", "spgemm_profile_begin", "spgemm_profile_end",
-    "spgemm_copy", "spgemm", "load", "BatchPlan", "spgemm_batched_symbolic", "spgemm_batched", "spgemm_batch",
+    "spgemm_copy", "spgemm", "spgemm_csc", "load", "BatchPlan", "spgemm_batched_symbolic", "spgemm_batched",
+    "spgemm_batch",
 ]
 
 
@@ -252,6 +253,15 @@ def spgemm(A: DeviceCsx, B: DeviceCsx, precision: str = "f64", tune: dict | None
     finally:
         plan.close()
     return DeviceCsr(A.nrows, B.ncols, rowptr, colidx[:nnz], val[:nnz])
+
+
+def spgemm_csc(A: DeviceCsx, B: DeviceCsx, precision: str = "f64", tune: dict | None = None,
+               stream=None) -> DeviceCsx:
+    """C = A*B returned in CSC (A CSC, B CSR), with no extra pass: C in CSC
+    has the arrays of C^T = B^T * A^T in CSR, and B^T in CSC (A^T in CSR)
+    are B's (A's) own arrays read the other way round."""
+    ct = spgemm(B.transpose_view(), A.transpose_view(), precision=precision, tune=tune, stream=stream)
+    return DeviceCsx(A.nrows, B.ncols, ct.rowptr, ct.colidx, ct.val)
 
 
 # ---------------------------------------------------------------- batches
