@@ -391,12 +391,15 @@ struct RowFlopDst {
     __device__ void side_commit(uint64_t v) const { atomic_max_agent(&info->maxnormal, v); }
 };
 
-// Bin cut.  With H = T - maxnormal and row weight g(r) = R[r] + c*r
-// (c = ceil(H / 2^rowbits) >= 1), a row starts a new bin when it is the
-// first row, when it or its predecessor is big (row flop > T/2), or when
-// floor(g/H) differs from its predecessor's.  A bin of normal rows then
-// holds < H + maxnormal <= T tuples and < H/c <= 2^rowbits rows; a big row
-// is a bin by itself.  Payload: (count of starts) << 31 | last start row.
+// Bin cut.  With H = T - maxnormal, cap = 2^rowbits - 1 and row weight
+// g(r) = R[r] + c*r (c = ceil(H / cap) >= 1), a row starts a new bin when it
+// is the first row, when it or its predecessor is big (row flop > T/2), or
+// when floor(g/H) differs from its predecessor's.  Rows s..e of one bin of
+// normal rows have g(e) - g(s) <= H - 1 and g(e) - g(s) >= c*(e - s), so the
+// bin holds <= H - 1 + maxnormal < T tuples and e - s + 1 <= cap rows; a big
+// row is a bin by itself.  The row part of a key is then at most
+// 2^rowbits - 2, so no real key equals the all-ones sentinel, even at
+// column 2^colbits - 1.  Payload: (count of starts) << 31 | last start row.
 struct BinOp {
     static __device__ __forceinline__ uint64_t identity() { return 0; }
     static __device__ __forceinline__ uint64_t combine(uint64_t a, uint64_t b) {
@@ -415,7 +418,7 @@ struct BinSrc {
     __device__ uint64_t operator()(int64_t r) const {
         const uint64_t thalf = T / 2;
         const uint64_t H = T - info->maxnormal;
-        const uint64_t cap = rowbits >= 40 ? (1ull << 40) : (1ull << rowbits);
+        const uint64_t cap = (rowbits >= 40 ? (1ull << 40) : (1ull << rowbits)) - 1;
         uint64_t c = (H + cap - 1) / cap;
         c = c < 1 ? 1 : c;
         bool start = (r == 0);

@@ -97,7 +97,8 @@ def test_batch_sizes_like_workload(pb):
 def test_graph_capture_replays(pb):
     """The numeric step enqueues work only (no sync): capture it in a HIP
     graph and replay it several times, with eager work and synchronisations
-    between replays; every replay must equal the eager result."""
+    between replays; every replay must equal the eager result and the
+    oracle."""
     import torch
 
     _say("hipGraph capture of the batched numeric step")
@@ -111,6 +112,7 @@ def test_graph_capture_replays(pb):
              torch.empty(max(f, 1), dtype=torch.float64, device="cuda")) for (a, _), f in zip(pairs, plan.flops)]
     nnz = pb.spgemm_batched(plan, pairs, ws, outs, sync=True)
     eager = [(rp.clone(), ci[:z].clone(), cv[:z].clone()) for (rp, ci, cv), z in zip(outs, nnz)]
+    refs = [_ref(a, b) for a, b in probs]
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -128,10 +130,11 @@ def test_graph_capture_replays(pb):
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        for (rp, ci, cv), (erp, eci, ecv), z in zip(outs, eager, nnz):
+        for (rp, ci, cv), (erp, eci, ecv), z, ref in zip(outs, eager, nnz, refs):
             assert torch.equal(rp, erp), f"replay {rep}: row pointers"
             assert torch.equal(ci[:z], eci), f"replay {rep}: columns"
             assert torch.allclose(cv[:z], ecv, rtol=1e-12, atol=0), f"replay {rep}: values"
+            _check(dict(rowptr=rp.cpu().numpy(), colidx=ci[:z].cpu().numpy(), val=cv[:z].cpu().numpy()), ref, "f64")
     plan.close()
 
 
@@ -145,3 +148,64 @@ def test_batch_with_wide_row_is_rejected(pb):
         pb.spgemm_batch(pairs, tune={"tile_tuples": 256})
     assert ei.value.name == "PB_ERR_UNSUPPORTED"
 
+
+
+def _compare_device(c, ref, precision, what):
+    """C (device CSR) against oracle arrays (ptr/idx/val/absval), on the device."""
+    import torch
+
+    assert torch.equal(c.rowptr, torch.from_numpy(ref["ptr"]).cuda()), f"{what}: row pointers"
+    assert torch.equal(c.colidx, torch.from_numpy(ref["idx"]).cuda()), f"{what}: columns"
+    err = (c.val.double() - torch.from_numpy(ref["val"]).cuda()).abs()
+    bound = torch.from_numpy(ref["absval"]).cuda() * TOL[precision]
+    assert bool(torch.all(err <= bound).item()), f"{what}: values beyond {TOL[precision]} x N"
+
+
+def _compare_rows(c, ref, rows, precision, what):
+    rp = c.rowptr.cpu().numpy()
+    ci = c.colidx.cpu().numpy()
+    cv = c.val.cpu().numpy().astype(np.float64)
+    for s, r in enumerate(rows):
+        lo, hi = rp[r], rp[r + 1]
+        rlo, rhi = ref["ptr"][s], ref["ptr"][s + 1]
+        assert np.array_equal(ci[lo:hi], ref["idx"][rlo:rhi]), f"{what}: row {r} structure"
+        assert np.all(np.abs(cv[lo:hi] - ref["val"][rlo:rhi]) <= TOL[precision] * ref["absval"][rlo:rhi]), \
+            f"{what}: row {r} values"
+
+
+@pytest.mark.slow
+def test_batch_512_workload_vs_oracle(pb):
+    """The benchmarked batch itself (512 ER products, n_i log-uniform in
+    [2^10, 2^17], d_i in 2..32, values U(-1,1), 5.9e9 multiplications), in
+    the benchmark's configuration (2048-tuple bins, 1024-tuple expand
+    chunks) and with 4096-tuple bins, FP64 and FP32c.  Whole C against the
+    oracle for every 4th problem of the FP64 2048-tuple run and every 16th
+    of the others; 8 random rows of every other problem of the FP64
+    2048-tuple run; CSR invariants of every problem in every run."""
+    import os
+
+    import torch
+
+    from workloads import batched_er_problems
+
+    nth = len(os.sched_getaffinity(0))
+    _say("batch of 512: generating")
+    probs = list(batched_er_problems(512))
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    rng = np.random.default_rng(512)
+    for precision, tile, stride in (("f64", 2048, 4), ("f32c", 2048, 16), ("f64", 4096, 16), ("f32c", 4096, 16)):
+        _say(f"batch of 512: {precision}, tile {tile}")
+        outs = pb.spgemm_batch(pairs, precision=precision, tune={"tile_tuples": tile, "expand_chunk": 1024})
+        for i, ((a, b), c) in enumerate(zip(probs, outs)):
+            what = f"{precision} tile {tile} problem {i}"
+            rp = c.rowptr
+            flop = int(np.dot(np.diff(a.ptr), np.diff(b.ptr)))
+            assert int(rp[0]) == 0 and int(rp[-1]) == c.nnz <= flop, f"{what}: row pointer ends"
+            assert bool(torch.all(rp[1:] >= rp[:-1]).item()), f"{what}: row pointers decrease"
+            if i % stride == 0:
+                _compare_device(c, oracle.spgemm_rows(a, b, None, nthreads=nth), precision, what)
+            elif stride == 4:
+                rows = np.unique(rng.integers(0, a.nrows, 8))
+                _compare_rows(c, oracle.spgemm_rows(a, b, rows, nthreads=nth), rows, precision, what)
+        del outs
+        torch.cuda.empty_cache()

@@ -1,8 +1,10 @@
 """GPU parity for the full-size R-MAT product C = A*A (scale 20, edge
 factor 16): 7e10 tuples and 2.4e10 entries of C, so the product runs in
 row-range rounds into one reused buffer.  The oracle computes sampled rows
-(the heaviest hub rows and random rows) exactly; every round is also checked
-for properties that hold at any size."""
+(the heaviest hub rows and random rows) and a block of consecutive rows at
+the start of the lightest round (up to 3e8 multiplications, row pointers
+included) exactly; every round is also checked for properties that hold at
+any size."""
 import os
 import sys
 
@@ -40,12 +42,28 @@ def setup():
     rows = np.unique(np.concatenate([np.argsort(rowflop)[-24:], rng.integers(0, a.nrows, 40)]))
     _say(f"oracle on {rows.size} sampled rows ({int(rowflop[rows].sum())} flop)")
     ref = oracle.spgemm_rows(ac, a, rows, nthreads=len(os.sched_getaffinity(0)))
-    return pb, torch, a, ac, rows, ref
+    return pb, torch, a, ac, rows, ref, rowflop
+
+
+_BLOCK = {}
+
+
+def _block_ref(ac, a, rowflop, r0, r1, nth):
+    """Oracle rows [r0, r1') where r1' <= r1 keeps the block's
+    multiplications under 3e8 (at least one row)."""
+    key = (r0, r1)
+    if key not in _BLOCK:
+        cum = np.cumsum(rowflop[r0:r1])
+        nrow = max(1, int(np.searchsorted(cum, 3e8, side="right")))
+        rows = np.arange(r0, r0 + nrow, dtype=np.int64)
+        _say(f"oracle on rows [{r0}, {r0 + nrow}) of the lightest round ({int(cum[nrow - 1])} flop)")
+        _BLOCK[key] = (rows, oracle.spgemm_rows(ac, a, rows, nthreads=nth))
+    return _BLOCK[key]
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32c"])
 def test_rmat_scale20_rounds(setup, precision):
-    pb, torch, a, ac, rows, ref = setup
+    pb, torch, a, ac, rows, ref, rowflop = setup
     A, B = pb.DeviceCsx.from_host(ac), pb.DeviceCsx.from_host(a)
     tune = {"round_tuples": ROUND_TUPLES}
     nsym = pb.spgemm_symbolic(A, B, precision, tune)
@@ -54,6 +72,8 @@ def test_rmat_scale20_rounds(setup, precision):
     rb, fl = pb.spgemm_plan_rounds(plan)
     assert rb[0] == 0 and rb[-1] == a.nrows and sum(fl) == plan.info()["slots"] >= plan.flop
     _say(f"{precision}: flop {plan.flop}, {len(fl)} rounds, workspace {plan.workspace_bytes / 1e9:.1f} GB")
+    light = int(np.argmin(fl))
+    brows, bref = _block_ref(ac, a, rowflop, rb[light], rb[light + 1], len(os.sched_getaffinity(0)))
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     maxrows = max(rb[i + 1] - rb[i] for i in range(len(fl)))
     rp = torch.empty(maxrows + 1, dtype=torch.int64, device="cuda")
@@ -88,6 +108,17 @@ def test_rmat_scale20_rounds(setup, precision):
                 assert np.array_equal(got_c, want_c), f"row {row}: structure"
                 assert np.all(np.abs(got_v - want_v) <= TOL[precision] * nrm), f"row {row}: values"
                 seen += 1
+        if r == light:
+            # a block of consecutive rows at the round's start: row
+            # pointers (relative to the block's first row) and every entry
+            h = p.cpu().numpy()
+            g0 = int(h[0])
+            g1 = int(h[brows.size])
+            assert np.array_equal(h[: brows.size + 1] - g0, bref["ptr"]), f"round {r}: row pointers of the block"
+            assert np.array_equal(ci[g0:g1].cpu().numpy(), bref["idx"]), f"round {r}: columns of the block"
+            gv = cv[g0:g1].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(gv - bref["val"]) <= TOL[precision] * bref["absval"]), f"round {r}: block values"
+            _say(f"{precision}: round {r}: block of {brows.size} rows, {g1 - g0} entries equal the oracle")
         if r % 4 == 0:
             _say(f"{precision}: round {r + 1}/{len(fl)} ok")
     assert seen == rows.size

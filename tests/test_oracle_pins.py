@@ -269,6 +269,10 @@ def test_rows_entry_point_matches_full(oracle_mod):
         assert np.array_equal(r["idx"][r["ptr"][s]:r["ptr"][s + 1]], c["colidx"][lo:hi])
         assert np.array_equal(r["val"][r["ptr"][s]:r["ptr"][s + 1]], c["val"][lo:hi])
         assert np.array_equal(r["absval"][r["ptr"][s]:r["ptr"][s + 1]], c["absval"][lo:hi])
+    # all rows at once (rows=None) is C in CSR, bit for bit
+    r = oracle_mod.spgemm_rows(a, b, None)
+    for key, full in (("ptr", "rowptr"), ("idx", "colidx"), ("val", "val"), ("absval", "absval")):
+        assert np.array_equal(r[key], c[full])
 
 
 @pytest.mark.parametrize("n,d", [(4096, 4), (1000, 16), (300, 1), (64, 64)])
