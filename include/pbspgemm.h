@@ -192,6 +192,24 @@ pb_status spgemm_numeric(pb_plan *plan, const pb_csx *A_csc, const pb_csx *B_csr
                          int64_t *nnzC, void *hip_stream);
 
 /*
+ * Numeric step that allocates nothing and takes no workspace: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same contract as
+ * spgemm_numeric, except that the numeric workspace is a device array
+ * inside the library of PB_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held
+ * until the process ends (the GPU is the current device; hip_stream must
+ * belong to it).  A plan whose reported workspace_bytes exceed that size is
+ * rejected with PB_ERR_WORKSPACE before any launch.  The call makes no
+ * hipMalloc / hipFree or other allocating call.  Every call on one GPU uses
+ * the same array, and the array keeps the last call's contents (the call
+ * clears what must start at zero itself): calls that overlap on one GPU
+ * (other host threads, or other streams not ordered with this one) race.
+ */
+#define PB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pb_status spgemm_numeric_noalloc(pb_plan *plan, const pb_csx *A_csc, const pb_csx *B_csr, pb_csr_out *C,
+                                 int64_t *nnzC, void *hip_stream);
+
+/*
  * Row-range rounds (the paper's partitioned formulation for products whose
  * expanded tuples exceed memory, Sections 2.2 and 3.4).  A plan built with
  * tune->round_tuples > 0 and more tuples than that, or with rows wider than

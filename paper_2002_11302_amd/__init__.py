@@ -12,11 +12,11 @@ import ctypes
 import dataclasses
 
 from . import _binding as _b
-from ._binding import PHASES, PbError  # noqa: F401
+from ._binding import NOALLOC_SCRATCH_BYTES, PHASES, PbError  # noqa: F401
 
 __all__ = [
     "DeviceCsx", "DeviceCsr", "Plan", "PbError", "PHASES",
-    "spgemm_symbolic", "spgemm_numeric", "spgemm_plan_info", "spgemm_plan_destroy",
+    "spgemm_symbolic", "spgemm_numeric", "spgemm_numeric_noalloc", "NOALLOC_SCRATCH_BYTES", "spgemm_plan_info", "spgemm_plan_destroy",
     "spgemm_status_string", "spgemm_last_error", "spgemm_profile_begin", "spgemm_profile_end",
     "spgemm_copy", "spgemm", "spgemm_csc", "load", "BatchPlan", "spgemm_batched_symbolic", "spgemm_batched",
     "spgemm_batch",
@@ -166,6 +166,23 @@ def spgemm_numeric(plan: Plan, A: DeviceCsx, B: DeviceCsx, workspace, C_rowptr, 
     wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _b.check(lib.spgemm_numeric(plan.handle, ctypes.byref(a), ctypes.byref(b), wsp, wsb, ctypes.byref(out),
                                 ctypes.byref(nnz) if sync else None, _stream(stream)), "spgemm_numeric")
+    return int(nnz.value) if sync else None
+
+
+def spgemm_numeric_noalloc(plan: Plan, A: DeviceCsx, B: DeviceCsx, C_rowptr, C_colidx, C_val,
+                           sync: bool = True, stream=None):
+    """Numeric step into caller tensors with no workspace argument: the
+    library's own per-GPU device scratch of NOALLOC_SCRATCH_BYTES holds the
+    workspace, and nothing is allocated.  Returns nnz(C) when ``sync``."""
+    lib = _b.lib()
+    a, b = A._abi(), B._abi()
+    cap = int(C_colidx.numel())
+    out = _b.PbCsrOut(C_rowptr.data_ptr(), C_colidx.data_ptr() if cap else None,
+                      C_val.data_ptr() if cap else None, cap)
+    nnz = ctypes.c_int64(-1)
+    _b.check(lib.spgemm_numeric_noalloc(plan.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(out),
+                                        ctypes.byref(nnz) if sync else None, _stream(stream)),
+             "spgemm_numeric_noalloc")
     return int(nnz.value) if sync else None
 
 

@@ -20,6 +20,7 @@ STATUS_NAMES = {
 PRECISIONS = {"f64": 0, "f32c": 1}
 PB_NPHASES = 5
 PHASES = ("symbolic", "expand", "sort_compress", "row_counts", "wide_partition")
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PB_NOALLOC_SCRATCH_BYTES
 
 
 class PbError(RuntimeError):
@@ -72,6 +73,8 @@ SIGNATURES = {
                                        ctypes.POINTER(_sz)]),
     "spgemm_numeric": (ctypes.c_int, [_vp, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx), _vp, _sz,
                                       ctypes.POINTER(PbCsrOut), ctypes.POINTER(_i64), _vp]),
+    "spgemm_numeric_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx),
+                                              ctypes.POINTER(PbCsrOut), ctypes.POINTER(_i64), _vp]),
     "spgemm_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(PbPlanInfo)]),
     "spgemm_plan_rounds": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "spgemm_numeric_round": (ctypes.c_int, [_vp, ctypes.POINTER(PbCsx), ctypes.POINTER(PbCsx), _i64, _vp, _sz,

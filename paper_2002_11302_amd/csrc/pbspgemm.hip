@@ -1009,6 +1009,42 @@ pb_status numeric_status(uint32_t err, int64_t total, int64_t capacity) {
     return PB_OK;
 }
 
+namespace {
+
+pb_status numeric_impl(pb_plan *p, const pb_csx *A, const pb_csx *B, void *workspace, size_t workspace_bytes,
+                       pb_csr_out *C, int64_t *nnzC, void *hip_stream);
+
+// Device scratch of spgemm_numeric_noalloc: the numeric workspace of plans
+// that fit it, in a file-scope device array, so that the call allocates
+// nothing.  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, not the
+// device array: the device address comes from hipGetSymbolAddress, taken
+// once per device (with that device current) and kept in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = PB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+pb_status noalloc_scratch(void **out) {
+    int dev = -1;
+    PB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PB_ERR_UNSUPPORTED, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PB_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *spgemm_status_string(pb_status s) {
@@ -1108,6 +1144,29 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
 pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *workspace, size_t workspace_bytes,
                          pb_csr_out *C, int64_t *nnzC, void *hip_stream) {
     g_last_error.clear();
+    return numeric_impl(p, A, B, workspace, workspace_bytes, C, nnzC, hip_stream);
+}
+
+pb_status spgemm_numeric_noalloc(pb_plan *p, const pb_csx *A, const pb_csx *B, pb_csr_out *C, int64_t *nnzC,
+                                 void *hip_stream) {
+    g_last_error.clear();
+    if (!p) return fail(PB_ERR_ARG, "plan is NULL");
+    if (p->ws_bytes > kNoAllocScratchBytes)
+        return fail(PB_ERR_WORKSPACE,
+                    "the plan's numeric workspace (%zu bytes) exceeds the %zu-byte device scratch of "
+                    "spgemm_numeric_noalloc; use spgemm_numeric with a workspace",
+                    p->ws_bytes, kNoAllocScratchBytes);
+    void *ws = nullptr;
+    PB_TRY(noalloc_scratch(&ws));
+    return numeric_impl(p, A, B, ws, kNoAllocScratchBytes, C, nnzC, hip_stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+pb_status numeric_impl(pb_plan *p, const pb_csx *A, const pb_csx *B, void *workspace, size_t workspace_bytes,
+                       pb_csr_out *C, int64_t *nnzC, void *hip_stream) {
     if (!p) return fail(PB_ERR_ARG, "plan is NULL");
     if (p->count != 1) return fail(PB_ERR_ARG, "the plan is a batch plan: use spgemm_batched");
     PB_TRY(check_csx(A, "A"));
@@ -1161,6 +1220,10 @@ pb_status spgemm_numeric(pb_plan *p, const pb_csx *A, const pb_csx *B, void *wor
     }
     return PB_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 pb_status spgemm_plan_rounds(const pb_plan *p, int64_t *nrounds, int64_t *row_begin, int64_t *flop_per_round) {
     if (!p || !nrounds) return fail(PB_ERR_ARG, "NULL argument");
