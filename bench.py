@@ -9,10 +9,18 @@ merge, CSR emission).  Inputs are resident in HBM before timing starts.
 Workload (default): Erdos-Renyi A and B, n = 2^20, exactly 16 nonzeros per
 column, values U[0,1) in double, C = A*B, FP64 path.
 
+Beside the headline the default run times the other workloads of the
+path, each reported under "extras": the same product with FP32 tuple values
+and compensated sums (speedup and error against FP64), the AMG Galerkin
+chain, the 512-product batch (against the plain path run product by
+product), and R-MAT scale 20 in row-range rounds.  The CPU oracle computes
+the whole headline product on the host (cpu_baseline), and its output also
+checks this run's GPU results.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--precision f64|f32c] [--no-cpu-baseline] [--extras]
-                    [--amg] [--batched] [--rmat] [--sweep]
+    python bench.py [--steps K] [--warmup W] [--precision f64|f32c] [--no-cpu-baseline]
+                    [--quick [--extras] [--amg] [--batched] [--rmat]] [--sweep]
 """
 from __future__ import annotations
 
@@ -97,6 +105,13 @@ def make_step(pb, torch, A, B, precision, tune=None):
     return step, flop, (rowptr, colidx, val)
 
 
+def make_step_outputs(out):
+    """(rowptr, colidx, val) of a make_step output trimmed to nnz(C)."""
+    rp, ci, cv = out
+    n = int(rp[-1].item())
+    return rp, ci[:n], cv[:n]
+
+
 def time_steps(torch, pb, step, steps, warmup):
     for _ in range(warmup):
         step()
@@ -129,41 +144,153 @@ def copy_bandwidth(pb, torch, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(a, b):
+def cpu_baseline(a, b, torch=None, gpu_results=None):
+    """The oracle on every host thread, over the whole benchmark product
+    (row by row).  With gpu_results {precision: (rowptr, colidx, val)} on the
+    device, the same oracle output also checks them: structure equal, and the
+    largest |difference| / N with N = |A||B| per entry."""
     import oracle
 
     threads = len(os.sched_getaffinity(0))
     oracle.build(force=False)
     t = time.perf_counter()
-    r = oracle.spgemm_cols(a, b, None, nthreads=threads)
+    r = oracle.spgemm_rows(a, b, None, nthreads=threads)
     dt = time.perf_counter() - t
     flop = oracle.flop(a.ptr, b.ptr)
+    out = {"value": round(2.0 * flop / dt / 1e9, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
+           "sample": f"full product: all {a.nrows} rows of the ER n=2^20 d=16 A*B workload, FP64; "
+                     f"{dt:.2f} s wall on {threads} host threads"}
+    check = {}
+    if gpu_results:
+        ptr = torch.from_numpy(r["ptr"]).cuda()
+        idx = torch.from_numpy(r["idx"]).cuda()
+        val = torch.from_numpy(r["val"]).cuda()
+        nrm = torch.from_numpy(r["absval"]).cuda()
+        for prec, (rp, ci, cv) in gpu_results.items():
+            same = bool(torch.equal(rp, ptr)) and bool(torch.equal(ci, idx))
+            err = float(((cv.double() - val).abs() / nrm.clamp_min(1e-300)).max().item()) if same and val.numel() else None
+            check[prec] = {"structure_equal": same, "max_err_over_N": err}
+        del ptr, idx, val, nrm
     del r
-    return {"value": round(2.0 * flop / dt / 1e9, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
-            "sample": f"full product: all {b.ncols} output columns of the ER n=2^20 d=16 A*B workload, FP64; "
-                      f"{dt:.2f} s wall on {threads} host threads"}
+    return out, check
 
 
-def fp32c_vs_f64(pb, torch, A, B):
-    """Max |C_f32c - C_f64| / |C_f64| over all of C, on the device.  For the
-    ER inputs (values in [0,1)) |C_f64| is N = |A||B| of each entry, and the
-    FP64 result itself is held to 1e-12 N of the oracle by the parity tests,
-    so this bounds the FP32c error over N.  Structure must be identical."""
+def _abs_csx(pb, X):
+    return pb.DeviceCsx(X.nrows, X.ncols, X.ptr, X.idx, X.val.abs())
+
+
+def fp32c_error(pb, torch, A, B, signed):
+    """Largest |C_f32c - C_f64| / N over all of C, where N = |A||B| per entry
+    (for signed inputs computed on the GPU as the FP64 product of |A| and |B|,
+    which has C's structure; for non-negative inputs N = C).  The FP64 result
+    is itself held to 1e-12 N of the oracle by the parity tests.  Also the
+    99.9th percentile.  Structure must be identical."""
     c64 = pb.spgemm(A, B, precision="f64")
     c32 = pb.spgemm(A, B, precision="f32c")
     assert torch.equal(c64.rowptr, c32.rowptr) and torch.equal(c64.colidx, c32.colidx), "FP32c structure differs"
-    nz = c64.val != 0
-    rel = (c32.val.double() - c64.val).abs()[nz] / c64.val.abs()[nz]
-    worst = float(rel.max().item()) if rel.numel() else 0.0
-    del c64, c32
+    if signed:
+        n = pb.spgemm(_abs_csx(pb, A), _abs_csx(pb, B), precision="f64")
+        assert torch.equal(n.colidx, c64.colidx)
+        nv = n.val
+    else:
+        nv = c64.val.abs()
+    nz = nv > 0
+    rel = (c32.val.double() - c64.val).abs()[nz] / nv[nz]
+    out = {"max": float(rel.max().item()) if rel.numel() else 0.0,
+           "p99.9": float(torch.quantile(rel[:: max(1, rel.numel() // 4_000_000)].float(), 0.999).item())
+           if rel.numel() else 0.0}
+    del c64, c32, rel
     torch.cuda.empty_cache()
-    return worst
+    return out
+
+
+def amg_f32c_error(pb, torch):
+    """FP32c against FP64 for both products of the AMG chain (the second on
+    the FP64 T), normalised by N = |A||B| of each entry."""
+    from workloads import Csx, amg_problem
+
+    A, P = amg_problem(128)
+    Ad = pb.DeviceCsx.from_host(Csx(A.nrows, A.ncols, A.ptr, A.idx, A.val, "csc"))
+    Pd = pb.DeviceCsx.from_host(P)
+    T = pb.spgemm(Ad, Pd)
+    Td = pb.DeviceCsx(T.nrows, T.ncols, T.rowptr, T.colidx, T.val)
+    out = {"T=A*P": fp32c_error(pb, torch, Ad, Pd, signed=True),
+           "Ac=R*T": fp32c_error(pb, torch, Pd.transpose_view(), Td, signed=True)}
+    del T, Td
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_f32c_error(pb, torch, count=512):
+    """FP32c against FP64 over every product of the batch, normalised by
+    N = |A_i||B_i| (both batches through the batched path)."""
+    from workloads import batched_er_problems
+
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in batched_er_problems(count)]
+    worst = 0.0
+    for lo in range(0, count, 64):  # 64 problems at a time bounds the memory
+        chunk = pairs[lo:lo + 64]
+        c64 = pb.spgemm_batch(chunk, precision="f64")
+        c32 = pb.spgemm_batch(chunk, precision="f32c")
+        nn = pb.spgemm_batch([(_abs_csx(pb, a), _abs_csx(pb, b)) for a, b in chunk], precision="f64")
+        for x, y, z in zip(c64, c32, nn):
+            assert torch.equal(x.colidx, y.colidx) and torch.equal(x.colidx, z.colidx), "FP32c structure differs"
+            nz = z.val > 0
+            if bool(nz.any().item()):
+                worst = max(worst, float(((y.val.double() - x.val).abs()[nz] / z.val[nz]).max().item()))
+        del c64, c32, nn
+        torch.cuda.empty_cache()
+    return {"max": worst}
+
+
+def _batch_plan(pb, torch, pairs, prec, tune):
+    nsym = pb.spgemm_batched_symbolic(pairs, prec, tune)
+    sym = torch.empty(nsym, dtype=torch.uint8, device="cuda")
+    plan = pb.spgemm_batched_symbolic(pairs, prec, tune, sym_ws=sym)
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+    return sym, plan, ws
+
+
+def _outputs(torch, pairs, flops, prec):
+    vdt = torch.float64 if prec == "f64" else torch.float32
+    return [(torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda"),
+             torch.empty(max(f, 1), dtype=torch.int32, device="cuda"),
+             torch.empty(max(f, 1), dtype=vdt, device="cuda")) for (a, _), f in zip(pairs, flops)]
+
+
+def _graph_ms(torch, launch, steps, warmup):
+    """Capture launch(stream) once in a HIP graph (after one eager run on the
+    side stream) and time its replays."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        launch(side)
+        side.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            launch(side)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def bench_batched(pb, torch, steps, warmup):
     """Batched ER workload: 512 products, n_i log-uniform in [2^10, 2^17],
-    d_i in {2..32}, values U[-1,1).  Numeric step captured once in a HIP graph
-    and replayed; compared with the plain FP64 path run product by product."""
+    d_i in {2..32}, values U[-1,1).  The autotuner picks the tile (bin width)
+    and the expand chunk for the batch's size class; the batch is timed as a
+    whole path (symbolic + numeric) and with its numeric step captured in
+    one HIP graph.  The baseline is the plain path run product by product
+    with every plan, workspace and output allocated beforehand (whole path:
+    symbolic + numeric per product; numeric: the 512 numeric calls captured
+    in one graph), so no allocation is inside any timed region."""
     from paper_2002_11302_amd import autotune
     from workloads import batched_er_problems, batched_er_sizes
 
@@ -174,40 +301,31 @@ def bench_batched(pb, torch, steps, warmup):
     log(f"batched: generated and uploaded 512 problems in {time.time() - t:.1f}s")
     res = {"workload": "512 ER products, n_i log-uniform in [2^10,2^17], d_i in {2..32}, values U[-1,1)"}
     for prec in ("f64", "f32c"):
-        vdt = torch.float64 if prec == "f64" else torch.float32
         cache = {}
 
         def prepared(tune):
             key = (tune["tile_tuples"], tune["expand_chunk"])
             if key not in cache:
                 cache.clear()
-                nsym = pb.spgemm_batched_symbolic(pairs, prec, tune)
-                sym = torch.empty(nsym, dtype=torch.uint8, device="cuda")
-                plan = pb.spgemm_batched_symbolic(pairs, prec, tune, sym_ws=sym)
-                ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
-                cache[key] = (sym, plan, ws)
+                cache[key] = _batch_plan(pb, torch, pairs, prec, tune)
             return cache[key]
 
-        flops = None
         outs = None
 
         def run(tune):
-            nonlocal flops, outs
+            nonlocal outs
             sym, plan, ws = prepared(tune)
             if outs is None:
-                flops = plan.flops
-                outs = [(torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda"),
-                         torch.empty(max(f, 1), dtype=torch.int32, device="cuda"),
-                         torch.empty(max(f, 1), dtype=vdt, device="cuda")) for (a, _), f in zip(pairs, plan.flops)]
+                outs = _outputs(torch, pairs, plan.flops, prec)
             pb.spgemm_batched(plan, pairs, ws, outs, sync=True)
 
         key = autotune.size_class(512, (dvec * dvec * nvec).tolist(), int(nvec.max()), prec)
         best = autotune.tune(run, key, log=log)
         tune = {"tile_tuples": best["tile_tuples"], "expand_chunk": best["expand_chunk"]}
         sym, plan, ws = prepared(tune)
-        run(tune)
+        nnz = pb.spgemm_batched(plan, pairs, ws, outs, sync=True)
         tot_flop = int(sum(plan.flops))
-        # whole path (symbolic + numeric) per step
+        tot_nnz = int(sum(nnz))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -216,56 +334,73 @@ def bench_batched(pb, torch, steps, warmup):
             p2.close()
         torch.cuda.synchronize()
         whole = (time.perf_counter() - t0) / steps
-        # numeric step as one graph
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(side):
-            pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=side)
-            side.synchronize()
-            with torch.cuda.graph(g, stream=side):
-                pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=side)
-        torch.cuda.synchronize()
-        for _ in range(warmup):
-            g.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            g.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        graph_ms = e0.elapsed_time(e1) / steps
-        nnz = sum(int(o[0][-1].item()) for o in outs)
+        graph_ms = _graph_ms(torch, lambda st: pb.spgemm_batched(plan, pairs, ws, outs, sync=False, stream=st),
+                             steps, warmup)
+        mb = sum(model_bytes(a.nrows, a.ncols, a.nnz, b.nnz, f, 0, prec)["total"]
+                 for (a, b), f in zip(pairs, plan.flops)) + (12 if prec == "f64" else 8) * tot_nnz
         res[prec] = {"tune": tune, "autotune_cached": best.get("cached"), "autotune_timings_ms": best.get("timings_ms"),
-                     "flop": tot_flop, "nnz_c": nnz,
+                     "flop": tot_flop, "nnz_c": tot_nnz,
                      "whole_path_ms": round(whole * 1e3, 3), "whole_path_GFLOPS": round(2 * tot_flop / whole / 1e9, 2),
                      "numeric_graph_ms": round(graph_ms, 3),
                      "numeric_graph_GFLOPS": round(2 * tot_flop / (graph_ms * 1e-3) / 1e9, 2),
-                     "model_GB_without_C": round(sum(model_bytes(a.nrows, a.ncols, a.nnz, b.nnz, f, 0, prec)["total"]
-                                           for (a, b), f in zip(pairs, plan.flops)) / 1e9, 2)}
+                     "model_GB": round(mb / 1e9, 2),
+                     "numeric_graph_model_GBps": round(mb / (graph_ms * 1e-3) / 1e9, 1),
+                     "numeric_graph_frac_of_8TBps": round(mb / (graph_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)}
         log(f"batched {prec}: {res[prec]['whole_path_GFLOPS']} GFLOPS whole path, "
             f"{res[prec]['numeric_graph_GFLOPS']} GFLOPS numeric graph")
-        del g, outs, cache
+        del outs, cache, sym, plan, ws
         outs = None
         torch.cuda.empty_cache()
-    # the plain FP64 path, one product at a time
-    outs = None
+    # the plain FP64 path, one product at a time, everything preallocated
+    plans = []
+    for a, b in pairs:
+        nsym = pb.spgemm_symbolic(a, b, "f64")
+        sym = torch.empty(max(nsym, 1), dtype=torch.uint8, device="cuda")
+        plans.append((sym, pb.spgemm_symbolic(a, b, "f64", sym_ws=sym)))
+    ws = torch.empty(max(p.workspace_bytes for _, p in plans), dtype=torch.uint8, device="cuda")
+    outs = _outputs(torch, pairs, [p.flop for _, p in plans], "f64")
+    for (a, b), (sym, p), o in zip(pairs, plans, outs):
+        pb.spgemm_numeric(p, a, b, ws, *o, sync=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in pairs:
-        pb.spgemm(a, b)
+    for _ in range(steps):
+        for (a, b), (sym, _), o in zip(pairs, plans, outs):
+            p = pb.spgemm_symbolic(a, b, "f64", sym_ws=sym)
+            pb.spgemm_numeric(p, a, b, ws, *o, sync=False)
+            p.close()
     torch.cuda.synchronize()
-    seq = time.perf_counter() - t0
-    res["sequential_f64_ms"] = round(seq * 1e3, 2)
-    res["sequential_f64_GFLOPS"] = round(2 * res["f64"]["flop"] / seq / 1e9, 2)
-    res["speedup_batched_f64_vs_sequential_f64"] = round(seq / (res["f64"]["whole_path_ms"] * 1e-3), 2)
-    res["speedup_batched_f32c_vs_sequential_f64"] = round(seq / (res["f32c"]["whole_path_ms"] * 1e-3), 2)
+    seq = (time.perf_counter() - t0) / steps
+
+    def seq_numeric(st):
+        for (a, b), (_, p), o in zip(pairs, plans, outs):
+            pb.spgemm_numeric(p, a, b, ws, *o, sync=False, stream=st)
+
+    seq_graph = _graph_ms(torch, seq_numeric, steps, warmup)
+    for _, p in plans:
+        p.close()
+    del plans, ws, outs
+    torch.cuda.empty_cache()
+    flop = res["f64"]["flop"]
+    res["sequential_f64"] = {"note": "plain path, one product at a time, plans/workspace/outputs preallocated",
+                             "whole_path_ms": round(seq * 1e3, 2), "whole_path_GFLOPS": round(2 * flop / seq / 1e9, 2),
+                             "numeric_graph_ms": round(seq_graph, 3),
+                             "numeric_graph_GFLOPS": round(2 * flop / (seq_graph * 1e-3) / 1e9, 2)}
+    for prec in ("f64", "f32c"):
+        res[f"speedup_batched_{prec}_vs_sequential_f64"] = {
+            "whole_path": round(seq / (res[prec]["whole_path_ms"] * 1e-3), 3),
+            "numeric_graph": round(seq_graph / res[prec]["numeric_graph_ms"], 3)}
+    res["speedup_batched_f32c_vs_batched_f64"] = {
+        "whole_path": round(res["f64"]["whole_path_ms"] / res["f32c"]["whole_path_ms"], 3),
+        "numeric_graph": round(res["f64"]["numeric_graph_ms"] / res["f32c"]["numeric_graph_ms"], 3)}
+    log(f"batched: sequential FP64 {seq * 1e3:.1f} ms whole path, {seq_graph:.1f} ms numeric graph")
     return res
 
 
 def bench_amg(pb, torch, steps, warmup):
-    """AMG Galerkin chain on the 128^3 7-point Laplacian: T = A*P, Ac = R*T."""
+    """AMG Galerkin chain on the 128^3 7-point Laplacian: T = A*P, Ac = R*T,
+    each product's symbolic and numeric step, every buffer allocated
+    beforehand.  T's nnz is read back (one sync) because it sizes the second
+    product's operand."""
     from workloads import Csx, amg_problem
 
     A, P = amg_problem(128)
@@ -273,33 +408,55 @@ def bench_amg(pb, torch, steps, warmup):
     Pd = pb.DeviceCsx.from_host(P)
     Rd = Pd.transpose_view()
     res = {"workload": "AMG R*(A*P), 7-point Laplacian 128^3, smoothed aggregation 2x2x2, omega=2/3"}
-    # multiplications of both products, from the plans of the first run
-    T0 = pb.spgemm(Ad, Pd)
-    f1 = pb.spgemm_symbolic(Ad, Pd, sym_ws=torch.empty(pb.spgemm_symbolic(Ad, Pd), dtype=torch.uint8, device="cuda"))
-    T0d = pb.DeviceCsx(T0.nrows, T0.ncols, T0.rowptr, T0.colidx, T0.val)
-    f2 = pb.spgemm_symbolic(Rd, T0d, sym_ws=torch.empty(pb.spgemm_symbolic(Rd, T0d), dtype=torch.uint8, device="cuda"))
-    flop_chain = f1.flop + f2.flop
-    res["flop"] = [f1.flop, f2.flop]
-    f1.close()
-    f2.close()
     for prec in ("f64", "f32c"):
+        vdt = torch.float64 if prec == "f64" else torch.float32
+        s1 = torch.empty(pb.spgemm_symbolic(Ad, Pd, prec), dtype=torch.uint8, device="cuda")
+        p1 = pb.spgemm_symbolic(Ad, Pd, prec, sym_ws=s1)
+        T = (torch.empty(Ad.nrows + 1, dtype=torch.int64, device="cuda"),
+             torch.empty(p1.flop, dtype=torch.int32, device="cuda"), torch.empty(p1.flop, dtype=vdt, device="cuda"))
+        ws1 = torch.empty(p1.workspace_bytes, dtype=torch.uint8, device="cuda")
+        nnz_t = pb.spgemm_numeric(p1, Ad, Pd, ws1, *T)
+        Tval64 = torch.empty(nnz_t, dtype=torch.float64, device="cuda")
+        Td = pb.DeviceCsx(Ad.nrows, Pd.ncols, T[0], T[1][:nnz_t], Tval64)
+        Tval64.copy_(T[2][:nnz_t])
+        s2 = torch.empty(pb.spgemm_symbolic(Rd, Td, prec), dtype=torch.uint8, device="cuda")
+        p2 = pb.spgemm_symbolic(Rd, Td, prec, sym_ws=s2)
+        Ac = (torch.empty(Rd.nrows + 1, dtype=torch.int64, device="cuda"),
+              torch.empty(p2.flop, dtype=torch.int32, device="cuda"), torch.empty(p2.flop, dtype=vdt, device="cuda"))
+        ws2 = torch.empty(p2.workspace_bytes, dtype=torch.uint8, device="cuda")
+        flop = p1.flop + p2.flop
+        p1.close()
+        p2.close()
+
         def chain():
-            T = pb.spgemm(Ad, Pd, precision=prec)
-            Td = pb.DeviceCsx(T.nrows, T.ncols, T.rowptr, T.colidx, T.val.to(torch.float64))
-            return T, pb.spgemm(Rd, Td, precision=prec)
+            q1 = pb.spgemm_symbolic(Ad, Pd, prec, sym_ws=s1)
+            n1 = pb.spgemm_numeric(q1, Ad, Pd, ws1, *T)  # syncs: nnz(T) sizes the next operand
+            q1.close()
+            if prec == "f64":
+                tv = T[2][:n1]
+            else:  # operands are double: the float T is widened
+                tv = Tval64[:n1]
+                tv.copy_(T[2][:n1])
+            Tn = pb.DeviceCsx(Ad.nrows, Pd.ncols, T[0], T[1][:n1], tv)
+            q2 = pb.spgemm_symbolic(Rd, Tn, prec, sym_ws=s2)
+            pb.spgemm_numeric(q2, Rd, Tn, ws2, *Ac, sync=False)
+            q2.close()
 
         for _ in range(warmup):
             chain()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            T, Ac = chain()
+            chain()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        flop = flop_chain
-        res[prec] = {"chain_ms": round(dt * 1e3, 3), "GFLOPS": round(2 * flop / dt / 1e9, 2),
-                     "nnz_T": T.nnz, "nnz_Ac": Ac.nnz}
+        nnz_ac = int(Ac[0][-1].item())
+        res[prec] = {"chain_ms": round(dt * 1e3, 3), "GFLOPS": round(2 * flop / dt / 1e9, 2), "flop": flop,
+                     "nnz_T": nnz_t, "nnz_Ac": nnz_ac}
         log(f"amg {prec}: {dt * 1e3:.3f} ms per chain")
+        del T, Ac, ws1, ws2, s1, s2, Tval64
+        torch.cuda.empty_cache()
+    res["f32c_speedup_vs_f64"] = round(res["f64"]["chain_ms"] / res["f32c"]["chain_ms"], 3)
     return res
 
 
@@ -371,7 +528,37 @@ def bench_rmat(pb, torch, steps, warmup, scale=20, edge_factor=16, round_tuples=
             res["f32c_speedup_vs_f64"] = round(base_sec / sec, 3)
         del ws, out, sym
         torch.cuda.empty_cache()
+    res["f32c_error_vs_f64_by_round"] = rmat_f32c_error(pb, torch, A, B, round_tuples)
     return res
+
+
+def rmat_f32c_error(pb, torch, A, B, round_tuples):
+    """FP32c against FP64 on two rounds of the R-MAT product (the lightest
+    and a middle one).  Both plans use run alignment 1, so their rounds cover
+    the same rows; values are U[0,1), so N = C."""
+    tune = {"round_tuples": round_tuples, "run_align": 1}
+    kept, out_err = {}, []
+    for prec in ("f64", "f32c"):
+        plan, sym, ws, out, nr = prepare_rounds(pb, torch, A, B, prec, tune)
+        rb, fl = pb.spgemm_plan_rounds(plan)
+        for r in sorted({int(np.argmin(fl)), nr // 2}):
+            n = pb.spgemm_numeric_round(plan, A, B, r, ws, *out)
+            rows = rb[r + 1] - rb[r]
+            if prec == "f64":
+                kept[r] = (rb[r], rows, out[0][: rows + 1].clone(), out[1][:n].clone(), out[2][:n].clone())
+                continue
+            r0, rows64, rp, ci, cv = kept.pop(r)
+            assert r0 == rb[r] and rows64 == rows, "rounds differ between precisions"
+            assert torch.equal(rp, out[0][: rows + 1]) and torch.equal(ci, out[1][:n]), "FP32c structure differs"
+            nz = cv != 0
+            rel = (out[2][:n].double() - cv).abs()[nz] / cv.abs()[nz]
+            out_err.append({"round": r, "rows": rows, "nnz": n,
+                            "f32c_max_err_over_N": float(rel.max().item()) if rel.numel() else 0.0})
+            del rp, ci, cv, rel
+        plan.close()
+        del ws, out, sym
+        torch.cuda.empty_cache()
+    return out_err
 
 
 SWEEP_ER = [(s, d) for s in (16, 18, 20, 22) for d in (4, 8, 16, 32)]
@@ -590,11 +777,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["f64", "f32c"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time FP32c (with its error) and the copy bandwidth")
-    ap.add_argument("--batched", action="store_true", help="also run the 512-product batched workload")
-    ap.add_argument("--amg", action="store_true", help="also run the AMG Galerkin chain")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the headline product (skip the FP32c, AMG, batched and R-MAT legs)")
+    ap.add_argument("--extras", action="store_true", help="with --quick: the FP32c leg")
+    ap.add_argument("--batched", action="store_true", help="with --quick: the 512-product batched leg")
+    ap.add_argument("--amg", action="store_true", help="with --quick: the AMG Galerkin chain leg")
     ap.add_argument("--rmat", action="store_true",
-                    help="also run R-MAT scale 20 C=A*A (row-range rounds, wide rows), FP64 and FP32c")
+                    help="with --quick: the R-MAT scale 20 C=A*A leg (row-range rounds, wide rows), FP64 and FP32c")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the scale x edge-factor sweep (ER A*B and R-MAT A*A, FP64) with the byte model, "
                          "sampled-row parity and the autotuner's choice per point")
@@ -633,7 +822,8 @@ def main():
     pb.load()
     assert torch.cuda.is_available(), "needs a GPU"
     a, b, A, B = build_inputs(pb, torch)
-    step, flop, (rowptr, _, _) = make_step(pb, torch, A, B, args.precision)
+    step, flop, rowptr_c = make_step(pb, torch, A, B, args.precision)
+    rowptr = rowptr_c[0]
     log(f"flop={flop}; timing {args.steps} steps after {args.warmup} warm-up")
     sec, prof = time_steps(torch, pb, step, args.steps, args.warmup)
     nnz_c = int(rowptr[-1].item())
@@ -678,36 +868,44 @@ def main():
     beta = copy_bandwidth(pb, torch)
     out["copy_GBps"] = round(beta, 1)
     out["roofline"]["frac_of_copy"] = round(achieved / beta, 4)
-    if args.extras:
-        log("extras: FP32c step and copy bandwidth")
+    gpu_results = {args.precision: make_step_outputs(rowptr_c)}
+    legs = {"f32c": args.extras, "amg": args.amg, "batched": args.batched, "rmat": args.rmat}
+    if not args.quick:
+        legs = {k: True for k in legs}
+    ex = out.setdefault("extras", {})
+    if legs["f32c"]:
         other = "f32c" if args.precision == "f64" else "f64"
-        step2, _, (rp2, _, _) = make_step(pb, torch, A, B, other)
+        log(f"leg: {other} on the same product")
+        step2, _, outs2 = make_step(pb, torch, A, B, other)
         sec2, prof2 = time_steps(torch, pb, step2, args.steps, args.warmup)
-        out["extras"] = {
-            f"{other}_GFLOPS": round(2.0 * flop / sec2 / 1e9, 3),
-            f"{other}_ms_per_step": round(sec2 * 1e3, 4),
-            f"{other}_phases_ms": {k: round(ms / max(n, 1), 5) for k, (ms, n) in prof2.items()},
-            "copy_GBps": out["copy_GBps"],
-        }
-        out["extras"][f"{other}_speedup_vs_{args.precision}"] = round(sec / sec2, 3)
+        gpu_results[other] = make_step_outputs(outs2)
+        ex[other] = {"GFLOPS": round(2.0 * flop / sec2 / 1e9, 3), "ms_per_step": round(sec2 * 1e3, 4),
+                     "phases_ms": {k: round(ms / max(n, 1), 5) for k, (ms, n) in prof2.items()},
+                     f"speedup_vs_{args.precision}": round(sec / sec2, 3)}
         if other == "f32c":
-            out["extras"]["f32c_max_rel_diff_vs_f64"] = fp32c_vs_f64(pb, torch, A, B)
-    if args.amg:
-        out.setdefault("extras", {})["amg"] = bench_amg(pb, torch, max(3, args.steps // 4), 1)
-    if args.batched:
-        out.setdefault("extras", {})["batched"] = bench_batched(pb, torch, max(2, args.steps // 10), 1)
-    if args.rmat:
-        out.setdefault("extras", {})["rmat"] = bench_rmat(pb, torch, 2, 1)
+            ex["f32c"]["error_vs_f64_over_N"] = fp32c_error(pb, torch, A, B, signed=False)
+    if legs["amg"]:
+        log("leg: AMG chain")
+        ex["amg"] = bench_amg(pb, torch, max(3, args.steps // 4), 1)
+        ex["amg"]["f32c_error_vs_f64_over_N"] = amg_f32c_error(pb, torch)
+    if legs["batched"]:
+        log("leg: batched")
+        ex["batched"] = bench_batched(pb, torch, max(2, args.steps // 10), 1)
+        ex["batched"]["f32c_error_vs_f64_over_N"] = batched_f32c_error(pb, torch)
+    if legs["rmat"]:
+        log("leg: R-MAT")
+        ex["rmat"] = bench_rmat(pb, torch, 2, 1)
     if args.sweep:
         import tempfile
 
-        ex = out.setdefault("extras", {})
         beta = out["copy_GBps"]
         ex["sweep_copy_GBps"] = beta
         ex["sweep"] = bench_sweep(pb, torch, beta, os.path.join(tempfile.mkdtemp(), "autotune.json"))
+    if not ex:
+        del out["extras"]
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(a, b)
+        out["cpu_baseline"], out["oracle_check_of_this_run"] = cpu_baseline(a, b, torch, gpu_results)
     print(json.dumps(out), flush=True)
 
 

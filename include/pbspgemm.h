@@ -108,14 +108,23 @@ typedef struct {
  *                 by a counting sort, then each bucket counts in LDS; needs
  *                 0 < nnz(A) < 2^32 and at most 2^25 rows, else PB_ERR_ARG);
  *                 0 = 2 when it applies, else 1.  C is the same either way
- *                 up to the order in which equal positions are summed. */
+ *                 up to the order in which equal positions are summed.
+ *   convert       how C's row pointers are formed (ConvertCSR): 1 = a
+ *                 key-only count pass gives the entries of every row and a
+ *                 scan over the rows gives the pointers, before the sort;
+ *                 2 = fused into the sort (each bin counts its distinct keys
+ *                 and takes the entries before it from the earlier bins by a
+ *                 decoupled look-back; measured slower, because each bin
+ *                 waits for the counts of the bins before it); 0 = 1.  C is
+ *                 the same either way. */
 typedef struct {
     int32_t tile_tuples;
     int32_t expand_chunk;
     int64_t round_tuples;
     int32_t run_align;
     int32_t row_count;
-    int32_t reserved[2];
+    int32_t convert;
+    int32_t reserved;
 } pb_tune;
 
 /* Plan facts (host copy, filled by the symbolic step). */
@@ -123,7 +132,7 @@ typedef struct {
     int64_t m, k, n;          /* C is m x n, inner dimension k */
     int64_t flop;             /* multiplications = number of expanded tuples */
     int64_t nbins;            /* bins of consecutive rows */
-    int64_t max_bin_tuples;   /* largest bin */
+    int64_t max_bin_tuples;   /* tuple slots of the largest bin (a wide row is a bin by itself) */
     int64_t max_row_flop;     /* largest row of C^ */
     int32_t tile_tuples, expand_chunk;
     int32_t col_bits;         /* bits of the column part of a packed key */
@@ -252,7 +261,13 @@ pb_status spgemm_numeric_round(pb_plan *plan, const pb_csx *A_csc, const pb_csx 
  * owned by the plan, then kernels), so it can be captured in a hipGraph and
  * replayed while the plan and the descriptor arrays' contents are unchanged;
  * otherwise nnzC is a host array of `count` entries (PB_ERR_CAPACITY names
- * the first problem whose capacity was too small).
+ * the first problem whose capacity was too small).  The pinned staging area
+ * is rewritten by every call: a call first waits (on the host) until the
+ * previous call's uploads from it are done, so calls on one plan may be
+ * enqueued back to back with different outputs.  Under stream capture that
+ * wait is skipped, and a replay uploads what the staging area holds at
+ * replay time, i.e. the descriptors of the latest call on the plan: capture
+ * after the last eager call on the plan, or keep a plan per captured graph.
  */
 pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A_csc, const pb_csx *B_csr, pb_precision prec,
                                   const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes, void *hip_stream,

@@ -61,11 +61,15 @@ class DeviceCsx:
         return DeviceCsx(self.ncols, self.nrows, self.ptr, self.idx, self.val)
 
     def _abi(self) -> _b.PbCsx:
+        torch = _torch()
         for t in (self.ptr, self.idx, self.val):
             if not t.is_cuda or not t.is_contiguous():
                 raise ValueError("DeviceCsx arrays must be contiguous device tensors")
-        assert self.ptr.dtype == _torch().int64 and self.idx.dtype == _torch().int32
-        assert self.val.dtype == _torch().float64
+        if self.ptr.dtype != torch.int64 or self.idx.dtype != torch.int32:
+            raise ValueError(f"DeviceCsx needs int64 pointers and int32 indices, got {self.ptr.dtype} / {self.idx.dtype}")
+        if self.val.dtype != torch.float64:
+            raise ValueError(f"DeviceCsx values must be float64 (operands are double in both precisions), got "
+                             f"{self.val.dtype}; an FP32c result becomes an operand with .val.double()")
         return _b.PbCsx(self.nrows, self.ncols, self.nnz, self.ptr.data_ptr(),
                         self.idx.data_ptr() if self.nnz else None, self.val.data_ptr() if self.nnz else None)
 
@@ -128,6 +132,7 @@ def _tune(tune):
     t.round_tuples = int(tune.get("round_tuples", 0))
     t.run_align = int(tune.get("run_align", 0))
     t.row_count = int(tune.get("row_count", 0))
+    t.convert = int(tune.get("convert", 0))
     return ctypes.byref(t)
 
 
@@ -276,7 +281,9 @@ def spgemm_csc(A: DeviceCsx, B: DeviceCsx, precision: str = "f64", tune: dict | 
                stream=None) -> DeviceCsx:
     """C = A*B returned in CSC (A CSC, B CSR), with no extra pass: C in CSC
     has the arrays of C^T = B^T * A^T in CSR, and B^T in CSC (A^T in CSR)
-    are B's (A's) own arrays read the other way round."""
+    are B's (A's) own arrays read the other way round.  With "f32c" the
+    values are float32; to use the result as an operand, convert them
+    (``DeviceCsx(c.nrows, c.ncols, c.ptr, c.idx, c.val.double())``)."""
     ct = spgemm(B.transpose_view(), A.transpose_view(), precision=precision, tune=tune, stream=stream)
     return DeviceCsx(A.nrows, B.ncols, ct.rowptr, ct.colidx, ct.val)
 

@@ -72,8 +72,9 @@ struct BigArgs {
     const int64_t *bigs;      // first tuple of wide row i (round-relative slot)
     const int64_t *bige;      // one past its last tuple
     const int64_t *cpre;      // partition chunks before wide row i (nbig + 1 entries)
-    const uint32_t *keys;     // the round's tuples (wide rows: key = column)
+    const uint32_t *keys;     // the round's tuples (wide rows: key = column; see TupleArr)
     const void *vals;
+    int kstride;              // 32-bit words from one key to the next (TupleArr<VT>::kKeyStride)
     uint32_t *chist;          // per chunk: tuples per window (2^lognwin entries)
     uint32_t *cnt_v;          // per virtual row: tuples (zeroed before the histogram)
     uint32_t *cur_v;          // per virtual row: fill cursor (zeroed)
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_hist(BigArgs a) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int64_t p = p0 + v * BLOCK + threadIdx.x;
-            kk[v] = p < e ? a.keys[p] : kSentinel;
+            kk[v] = p < e ? a.keys[p * a.kstride] : kSentinel;
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -186,8 +187,8 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
     }
     const uint32_t colmask = a.cb ? ((1u << a.cb) - 1u) : 0u;
     const uint32_t wmask = (1u << a.wbits) - 1u;
-    const VT *gv = (const VT *)a.vals;
-    VT *ov = (VT *)a.vals2;
+    const TupleArr<VT> in((void *)a.keys, (void *)a.vals);
+    const TupleArr<VT> out((void *)a.keys2, a.vals2);
     for (int64_t s0 = s; s0 < e; s0 += kBigSub) {
         const int nsub = (int)((e - s0) < kBigSub ? (e - s0) : kBigSub);
         for (int x = threadIdx.x; x < nwin; x += BLOCK) hsc[x] = 0;
@@ -199,12 +200,12 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int q = u * BLOCK + threadIdx.x;
-            col[u] = a.keys[s0 + (q < nsub ? q : nsub - 1)];
+            col[u] = in.key(s0 + (q < nsub ? q : nsub - 1));
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int q = u * BLOCK + threadIdx.x;
-            val[u] = gv[s0 + (q < nsub ? q : nsub - 1)];
+            val[u] = in.val(s0 + (q < nsub ? q : nsub - 1));
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -255,8 +256,7 @@ __global__ __launch_bounds__(BLOCK) void k_big_scatter(BigArgs a) {
             const uint32_t w = swin[q];
             const int64_t dest = vbase + (int64_t)cbase[w] + run[w] + (q - (int)hoff[w]);
             if ((uint64_t)dest < (uint64_t)a.nbigflop) {
-                a.keys2[dest] = skey[q];
-                ov[dest] = sval[q];
+                out.put(dest, skey[q], sval[q]);
             } else {
                 atomic_or_agent(a.err, (uint32_t)kErrBinOverflow);
             }
@@ -312,7 +312,7 @@ struct DenseArgs {
     const int32_t *list;      // virtual rows to do
     const uint64_t *count;    // how many
     const uint64_t *Rv;
-    const uint32_t *keys2;
+    const uint32_t *keys2;  // see TupleArr
     const void *vals2;
     int wbits, lognwin;
     uint32_t *rownnz_v;       // count mode
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_dense(DenseArgs a) {
     const int64_t cnt = (int64_t)*a.count;
     const uint32_t wmask = (1u << a.wbits) - 1u;
     const int ncol = 1 << a.wbits;
-    const VT *gv = (const VT *)a.vals2;
+    const TupleArr<VT> tv((void *)a.keys2, (void *)a.vals2);
     VT *cv = (VT *)a.cvals;
     for (int64_t it = blockIdx.x; it < cnt; it += gridDim.x) {
         const int64_t v = a.list[it];
@@ -355,8 +355,8 @@ __global__ __launch_bounds__(BLOCK) void k_dense(DenseArgs a) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t q = p0 + u * BLOCK < e ? p0 + u * BLOCK : e - 1;
-                kc[u] = a.keys2[q];
-                if (OUT) vv[u] = gv[q];
+                kc[u] = tv.key(q);
+                if (OUT) vv[u] = tv.val(q);
             }
             // lanes past the end repeat the last tuple with nothing to add
             // (its column is hit anyway), so every use of the loads is

@@ -117,54 +117,22 @@ __device__ uint64_t block_excl_scan(uint64_t v, uint64_t *lds, uint64_t &total) 
     return r;
 }
 
-// Decoupled look-back for tile `tile` of a chained scan whose tiles are
-// taken in ticket order.  Publishes the tile's aggregate, walks back over
-// predecessors until an inclusive prefix is found, publishes its own
-// inclusive prefix and returns the exclusive prefix.  Single thread.
-// Predecessor tiles belong to workgroups that started earlier and never wait
-// on later tiles, so every wait ends; the spin cap only guards against
-// corrupted status words.
+// Decoupled look-back, wave-wide.  Tiles (workgroups) are numbered in the
+// order they started (a ticket), and each publishes in status[tile] first
+// its aggregate (kFlagAgg), then its inclusive prefix (kFlagPrefix).
+// resolve_prefix_wave, called by one whole wave (all 64 lanes active) of a
+// tile that has published its aggregate `agg`, polls 64 predecessors per
+// round trip (lane l reads tile p - l), stops at the nearest inclusive
+// prefix, combines the payloads in between in tile order, publishes the
+// tile's inclusive prefix and returns its exclusive prefix in every lane
+// (identity for tile 0, which publishes its prefix directly).  Predecessor
+// tiles belong to workgroups that started earlier and never wait on later
+// tiles, so every wait ends; the spin cap only guards against corrupted
+// status words.
 template <class Op>
-__device__ uint64_t look_back(uint64_t *status, int64_t tile, uint64_t agg, uint32_t *err) {
-    if (tile == 0) {
-        atomic_store_agent(&status[0], kFlagPrefix | agg);
-        return Op::identity();
-    }
-    atomic_store_agent(&status[tile], kFlagAgg | agg);
-    uint64_t acc = Op::identity();
-    int64_t p = tile - 1;
-    uint32_t spins = 0;
-    while (true) {
-        uint64_t wv = atomic_load_agent(&status[p]);
-        uint64_t flag = wv & ~kPayload;
-        if (flag == 0) {
-            if (++spins > kSpinCap) {
-                atomic_or_agent(err, (uint32_t)kErrSpin);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        acc = Op::combine(wv & kPayload, acc);
-        if (flag == kFlagPrefix || p == 0) break;
-        --p;
-    }
-    atomic_store_agent(&status[tile], kFlagPrefix | Op::combine(acc, agg));
-    return acc;
-}
-
-// Wave-wide variant of look_back: the whole wave (all 64 lanes active)
-// polls 64 predecessors per round trip.  Lane l reads tile p - l; the walk
-// stops at the nearest inclusive prefix, and the payloads between are
-// combined in tile order.  Returns the exclusive prefix in every lane.
-template <class Op>
-__device__ uint64_t look_back_wave(uint64_t *status, int64_t tile, uint64_t agg, uint32_t *err) {
+__device__ uint64_t resolve_prefix_wave(uint64_t *status, int64_t tile, uint64_t agg, uint32_t *err) {
     const uint32_t lane = lane_id();
-    if (tile == 0) {
-        if (lane == 0) atomic_store_agent(&status[0], kFlagPrefix | agg);
-        return Op::identity();
-    }
-    if (lane == 0) atomic_store_agent(&status[tile], kFlagAgg | agg);
+    if (tile == 0) return Op::identity();
     uint64_t acc = Op::identity();  // combination of the tiles passed so far
     int64_t p = tile - 1;
     uint32_t spins = 0;
@@ -200,51 +168,12 @@ __device__ uint64_t look_back_wave(uint64_t *status, int64_t tile, uint64_t agg,
     return acc;
 }
 
-// Split form of the wave-wide look-back for tiles whose aggregate is known
-// well before their prefix is needed.  publish_agg stores the aggregate
-// (tile 0 stores its inclusive prefix directly); resolve_prefix_wave later
-// walks back from the predecessor, publishes the inclusive prefix and
-// returns the exclusive prefix in every lane of the calling wave.
-__device__ __forceinline__ void publish_agg(uint64_t *status, int64_t tile, uint64_t agg) {
-    atomic_store_agent(&status[tile], (tile == 0 ? kFlagPrefix : kFlagAgg) | agg);
-}
-
+// Publish the tile's aggregate (tile 0: its inclusive prefix) and resolve
+// its exclusive prefix: the whole look-back of a chained scan's tile.
 template <class Op>
-__device__ uint64_t resolve_prefix_wave(uint64_t *status, int64_t tile, uint64_t agg, uint32_t *err) {
-    const uint32_t lane = lane_id();
-    if (tile == 0) return Op::identity();
-    uint64_t acc = Op::identity();
-    int64_t p = tile - 1;
-    uint32_t spins = 0;
-    while (true) {
-        const int64_t idx = p - (int64_t)lane;
-        const uint64_t wv = idx >= 0 ? atomic_load_agent(&status[idx]) : kFlagPrefix;
-        const uint64_t flag = wv & ~kPayload;
-        const uint64_t pm = ballot(flag == kFlagPrefix);
-        const uint64_t zm = ballot(flag == 0);
-        const uint32_t f = pm ? (uint32_t)__builtin_ctzll(pm) : 64u;
-        const uint64_t need = f >= 63 ? ~0ull : ((2ull << f) - 1);
-        if (zm & need) {
-            if (++spins > kSpinCap) {
-                if (lane == 0) atomic_or_agent(err, (uint32_t)kErrSpin);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        uint64_t v = lane <= f ? (wv & kPayload) : Op::identity();
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint64_t o = __shfl_down(v, (unsigned)d, kWave);
-            if (lane + d < (uint32_t)kWave) v = Op::combine(o, v);
-        }
-        v = __shfl(v, 0, kWave);
-        acc = Op::combine(v, acc);
-        if (f < 64) break;
-        p -= kWave;
-    }
-    if (lane == 0) atomic_store_agent(&status[tile], kFlagPrefix | Op::combine(acc, agg));
-    return acc;
+__device__ uint64_t look_back_wave(uint64_t *status, int64_t tile, uint64_t agg, uint32_t *err) {
+    if (lane_id() == 0) atomic_store_agent(&status[tile], (tile == 0 ? kFlagPrefix : kFlagAgg) | agg);
+    return resolve_prefix_wave<Op>(status, tile, agg, err);
 }
 
 // largest i in [lo, hi) with a[i] <= x, given a[lo] <= x (a non-decreasing)

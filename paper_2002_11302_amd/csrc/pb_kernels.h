@@ -7,6 +7,14 @@ namespace pb {
 
 // ---------------------------------------------------------------------------
 // Facts the symbolic step leaves on the device (read back once).
+// Per-row facts: where the row's tuples start in the row-ordered tuple
+// array, and the row's index inside its bin.
+struct RowTab {
+    int64_t base;
+    uint32_t rl;
+    uint32_t bin;
+};
+
 struct SymInfo {
     uint64_t flop;       // Algorithm 3's multiplication count
     uint64_t slots;      // tuple slots: runs rounded up to the run alignment
@@ -14,6 +22,7 @@ struct SymInfo {
     uint64_t maxnormal;  // largest row flop among rows <= tile/2
     uint64_t maxrow;     // largest row flop
     uint64_t noversize;  // rows with more tuples than the tile
+    uint64_t maxbin;     // tuple slots of the largest bin
     uint32_t err;
     uint32_t pad;
 };
@@ -89,12 +98,54 @@ struct NoSide {
     __device__ void side_commit(uint64_t) const {}
 };
 
+// Where each A entry's run goes, one 64-bit word per entry: the run's first
+// tuple slot in the low 40 bits, the run's row inside its bin above them.
+// Bins therefore hold fewer than 2^24 rows, and products fewer than 2^40
+// tuple slots.
+constexpr int kEntSlotBits = 40;
+constexpr uint64_t kEntSlotMask = (1ull << kEntSlotBits) - 1;
+constexpr int kMaxBinRowBits = 64 - kEntSlotBits;
+__device__ __forceinline__ uint64_t ent_pack(uint64_t slot, uint32_t rl) {
+    return slot | ((uint64_t)rl << kEntSlotBits);
+}
+
 // Runs (the tuples of one A entry) occupy a multiple of `align` slots, so
 // that runs written by different waves never share a 32-byte sector of the
 // tuple arrays; the slots past a run's end hold the sentinel key.
 __device__ __forceinline__ int64_t run_slots(int64_t nb, int align) {
     return (nb + align - 1) / align * align;
 }
+
+// Tuple arrays.  FP64 tuples are two arrays (32-bit keys, double values).
+// FP32c tuples are one array of 8-byte words, key in the low half and the
+// float value's bits in the high half, so the run of tuples an A entry
+// writes is one contiguous segment.  Built from the (keys, vals) pair of a
+// workspace layout; for FP32c `keys` points at the word array and `vals` is
+// unused.
+template <class VT>
+struct TupleArr;
+template <>
+struct TupleArr<double> {
+    uint32_t *k;
+    double *v;
+    static constexpr int kKeyStride = 1;  // 32-bit words from one key to the next
+    __device__ TupleArr(void *keys, void *vals) : k((uint32_t *)keys), v((double *)vals) {}
+    __device__ void put(int64_t i, uint32_t key, double val) const {
+        k[i] = key;
+        v[i] = val;
+    }
+    __device__ uint32_t key(int64_t i) const { return k[i]; }
+    __device__ double val(int64_t i) const { return v[i]; }
+};
+template <>
+struct TupleArr<float> {
+    uint2 *t;
+    static constexpr int kKeyStride = 2;
+    __device__ TupleArr(void *keys, void *) : t((uint2 *)keys) {}
+    __device__ void put(int64_t i, uint32_t key, float val) const { t[i] = make_uint2(key, __float_as_uint(val)); }
+    __device__ uint32_t key(int64_t i) const { return t[i].x; }
+    __device__ float val(int64_t i) const { return __uint_as_float(t[i].y); }
+};
 
 // Algorithm 3: flop_k = nnz(A(:,k)) * nnz(B(k,:)); F = exclusive scan of
 // the column's tuple slots, nnz(A(:,k)) * run_slots(nnz(B(k,:))).
@@ -196,9 +247,11 @@ struct RowBucketArgs {
     uint32_t *roff;   // bucket order: the column when the slots field is
                       // saturated, then the run's offset in its row
     uint32_t *posof;  // per entry: its record
-    uint32_t *runpos;
     uint64_t *rowflop;
     SymInfo *info;
+    const RowTab *rowtab;  // per row: first slot and row inside its bin
+    uint64_t *entrec;             // bucket order: the record's run destination (ent_pack)
+    uint64_t *ent;                // entry order: the entry's run destination
 };
 
 template <int BLOCK>
@@ -344,7 +397,43 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t
     for (int i = threadIdx.x; i < kRowBucketRows && r0 + i < m; i += BLOCK) a.rowflop[r0 + i] = s_cnt[i];
 }
 
-// Pass 4: each entry's run offset from its record.
+// Pass 4 (after the row scan and the bin cut): one workgroup per bucket
+// holds its rows' first slots and rows-in-bin in LDS and turns every record's
+// run offset into the run's destination word.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_dest(RowBucketArgs a, int64_t m) {
+    __shared__ uint64_t s_base[kRowBucketRows];
+    __shared__ uint32_t s_rl[kRowBucketRows];
+    const int64_t b = blockIdx.x;
+    const int64_t r0 = b << kRowBucketBits;
+    for (int i = threadIdx.x; i < kRowBucketRows; i += BLOCK) {
+        if (r0 + i < m) {
+            const RowTab rt = a.rowtab[r0 + i];
+            s_base[i] = (uint64_t)rt.base;
+            s_rl[i] = rt.rl;
+        }
+    }
+    __syncthreads();
+    const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
+    constexpr int U = 4;
+    for (int64_t p = (int64_t)p0 + threadIdx.x; p < p1; p += (int64_t)BLOCK * U) {
+        uint32_t rc[U], off[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = p + u * BLOCK < p1 ? p + u * BLOCK : p1 - 1;  // unconditional loads overlap
+            rc[u] = a.rec[q];
+            off[u] = a.roff[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p + u * BLOCK >= p1) break;
+            const uint32_t row = rc[u] & (kRowBucketRows - 1);
+            a.entrec[p + u * BLOCK] = ent_pack(s_base[row] + off[u], s_rl[row]);
+        }
+    }
+}
+
+// Pass 5: each entry's run destination from its record.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_offsets(RowBucketArgs a) {
     const int64_t e0 = blockIdx.x * a.epw;
@@ -354,14 +443,19 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_offsets(RowBucketArgs a) {
         uint32_t ps[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) ps[u] = e + u * BLOCK < e1 ? a.posof[e + u * BLOCK] : 0u;
-        uint32_t off[U];
+        uint64_t d[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) off[u] = a.roff[ps[u]];
+        for (int u = 0; u < U; ++u) d[u] = a.entrec[ps[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (e + u * BLOCK < e1) a.runpos[e + u * BLOCK] = off[u];
+            if (e + u * BLOCK < e1) a.ent[e + u * BLOCK] = d[u];
     }
 }
+
+// Run destinations when the run offsets came from device atomics (k_rowflop):
+// one thread per entry of A, its row's facts gathered from the row table.
+__global__ __launch_bounds__(256) void k_entry_dest(int64_t nnz, const int32_t *ari, const uint32_t *runpos,
+                                                    const RowTab *rowtab, uint64_t *ent);
 
 // Exclusive scan of the bucket-major histogram, in place (total at [n]).
 struct HistSrc {
@@ -391,7 +485,7 @@ struct RowFlopDst {
     __device__ void side_commit(uint64_t v) const { atomic_max_agent(&info->maxnormal, v); }
 };
 
-// Bin cut.  With H = T - maxnormal, cap = 2^rowbits - 1 and row weight
+// Bin cut.  With H = T - maxnormal, cap = 2^min(rowbits, 24) - 1 and row weight
 // g(r) = R[r] + c*r (c = ceil(H / cap) >= 1), a row starts a new bin when it
 // is the first row, when it or its predecessor is big (row flop > T/2), or
 // when floor(g/H) differs from its predecessor's.  Rows s..e of one bin of
@@ -418,7 +512,8 @@ struct BinSrc {
     __device__ uint64_t operator()(int64_t r) const {
         const uint64_t thalf = T / 2;
         const uint64_t H = T - info->maxnormal;
-        const uint64_t cap = (rowbits >= 40 ? (1ull << 40) : (1ull << rowbits)) - 1;
+        const int cbits = rowbits < kMaxBinRowBits ? rowbits : kMaxBinRowBits;
+        const uint64_t cap = (1ull << cbits) - 1;
         uint64_t c = (H + cap - 1) / cap;
         c = c < 1 ? 1 : c;
         bool start = (r == 0);
@@ -441,13 +536,14 @@ struct BinSrc {
         return start ? ((1ull << 31) | (uint64_t)r) : 0;
     }
 };
-// Per-row facts the expand needs: where the row's tuples start in the
-// row-ordered tuple array, and the row's index inside its bin.
-struct RowTab {
-    int64_t base;
-    uint32_t rl;
-    uint32_t bin;
-};
+
+__global__ __launch_bounds__(256) void k_entry_dest(int64_t nnz, const int32_t *ari, const uint32_t *runpos,
+                                                    const RowTab *rowtab, uint64_t *ent) {
+    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (e >= nnz) return;
+    const RowTab rt = rowtab[ari[e]];
+    ent[e] = ent_pack((uint64_t)rt.base + runpos[e], rt.rl);
+}
 
 struct BinDst {
     RowTab *rowtab;
@@ -486,6 +582,29 @@ struct BinDst {
     __device__ void side_commit(uint64_t v) const { atomic_max_agent(&info->maxrow, v); }
 };
 
+// info->maxbin = the most tuple slots of any bin (bins < info->nbins).  A
+// grid-stride loop and one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_bin_max(const int64_t *binoff, int64_t maxbins, SymInfo *info) {
+    __shared__ uint64_t s_max[256 / kWave];
+    const int64_t nb = (int64_t)info->nbins < maxbins ? (int64_t)info->nbins : maxbins;
+    uint64_t v = 0;
+    for (int64_t b = blockIdx.x * (int64_t)256 + threadIdx.x; b < nb; b += (int64_t)gridDim.x * 256) {
+        const uint64_t sz = (uint64_t)(binoff[b + 1] - binoff[b]);
+        v = sz > v ? sz : v;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / kWave; ++i) v = s_max[i] > v ? s_max[i] : v;
+        if (v) atomic_max_agent(&info->maxbin, v);
+    }
+}
+
 // kstart[c] = column holding tuple c*C (c < nchunks); kstart[nchunks] = K-1.
 __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64_t *F, int32_t *kstart) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -514,13 +633,11 @@ struct ExpandArgs {
     const int64_t *F;
     const int32_t *kstart;
     const int64_t *acp;
-    const int32_t *ari;
     const double *av;
     const int64_t *brp;
     const int32_t *bci;
     const double *bv;
-    const uint32_t *runpos;  // offset of each A entry's run inside its row
-    const RowTab *rowtab;    // per row: first slot and index inside its bin
+    const uint64_t *ent;     // per A entry: its run's first slot and row in bin (ent_pack)
     uint32_t *keys;
     void *vals;
     int cb;
@@ -567,12 +684,11 @@ constexpr int kShortCols = 8;  // a chunk spanning more columns takes this path
 template <int W, class VT>
 __device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, const int64_t *__restrict__ acp,
                                              const int64_t *__restrict__ astart, const int64_t *__restrict__ brp,
-                                             const int32_t *__restrict__ ari, const uint32_t *__restrict__ runpos,
-                                             const RowTab *__restrict__ rowtab, const double *__restrict__ avv,
+                                             const uint64_t *__restrict__ ent, const double *__restrict__ avv,
                                              const int32_t *__restrict__ bci, const double *__restrict__ bvals,
-                                             uint32_t *__restrict__ keys, VT *__restrict__ vals,
-                                             uint32_t *__restrict__ err, int cb, int64_t flop, int64_t slot0,
-                                             int align, int64_t K, int64_t kb, int64_t t, const int64_t t1) {
+                                             const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
+                                             int64_t flop, int64_t slot0, int align, int64_t K, int64_t kb, int64_t t,
+                                             const int64_t t1) {
     const int lane = (int)lane_id();
     bool bad = false;
     while (t < t1) {
@@ -615,8 +731,8 @@ __device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, cons
                 ii[u] = q;
                 jj[u] = (uint32_t)r;
             }
-            int32_t ar[U];
-            uint32_t rp[U], col[U];
+            uint64_t en[U];
+            uint32_t col[U];
             double av[U], bvv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -624,15 +740,11 @@ __device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, cons
                 // padding slots read the run's last B entry
                 const uint32_t jb = own[u] ? (jj[u] < nbu[u] ? jj[u] : nbu[u] - 1u) : 0u;
                 const uint32_t bi = own[u] ? bsu[u] + jb : 0u;
-                ar[u] = ari[e];
-                rp[u] = runpos[e];
+                en[u] = ent[e];
                 av[u] = avv[e];
                 col[u] = (uint32_t)bci[bi];
                 bvv[u] = bvals[bi];
             }
-            RowTab rt[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) rt[u] = rowtab[ar[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!on[u]) continue;
@@ -640,11 +752,11 @@ __device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, cons
                     bad = true;
                     continue;
                 }
-                const int64_t slot = rt[u].base - slot0 + (int64_t)rp[u] + jj[u];
+                const int64_t slot = (int64_t)(en[u] & kEntSlotMask) - slot0 + jj[u];
                 const bool real = jj[u] < nbu[u];
+                const uint32_t rl = (uint32_t)(en[u] >> kEntSlotBits);
                 if ((uint64_t)slot < (uint64_t)flop) {
-                    keys[slot] = real ? ((rt[u].rl << cb) | col[u]) : kSentinel;
-                    vals[slot] = real ? (VT)(av[u] * bvv[u]) : (VT)0;
+                    tup.put(slot, real ? ((rl << cb) | col[u]) : kSentinel, real ? (VT)(av[u] * bvv[u]) : (VT)0);
                 } else {
                     bad = true;
                 }
@@ -666,13 +778,11 @@ __device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, cons
 template <int W, class VT>
 __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const int32_t *__restrict__ kstart,
                                             const int64_t *__restrict__ acp, const int64_t *__restrict__ astart,
-                                            const int64_t *__restrict__ brp, const int32_t *__restrict__ ari,
-                                            const uint32_t *__restrict__ runpos,
-                                            const RowTab *__restrict__ rowtab, const double *__restrict__ avv,
+                                            const int64_t *__restrict__ brp, const uint64_t *__restrict__ ent,
+                                            const double *__restrict__ avv,
                                             const int32_t *__restrict__ bci, const double *__restrict__ bvals,
-                                            uint32_t *__restrict__ keys, VT *__restrict__ vals,
-                                            uint32_t *__restrict__ err, int cb, int64_t flop, int64_t slot0,
-                                            int align, int64_t nchunks, int64_t K) {
+                                            const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
+                                            int64_t flop, int64_t slot0, int align, int64_t nchunks, int64_t K) {
     const uint32_t lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wave >= nchunks) return;
@@ -681,8 +791,8 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
     int64_t k = kstart[wave];
     int64_t t = t0;
     if (kstart[wave + 1] - k > kShortCols) {
-        expand_lanes<W, VT>(F, acp, astart, brp, ari, runpos, rowtab, avv, bci, bvals, keys, vals, err, cb, flop,
-                            slot0, align, K, k, t0, t1);
+        expand_lanes<W, VT>(F, acp, astart, brp, ent, avv, bci, bvals, tup, err, cb, flop, slot0, align, K, k, t0,
+                            t1);
         return;
     }
     while (t < t1) {
@@ -699,8 +809,7 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
         const int64_t as = astart ? astart[k] : acp[k];
         const int64_t seg_end = Fk1 < t1 ? Fk1 : t1;
         // column-local views: lanes index them with 32-bit offsets
-        const int32_t *ark = ari + as;
-        const uint32_t *rpk = runpos + as;
+        const uint64_t *enk = ent + as;
         const double *avk = avv + as;
         const int32_t *bck = bci + bs;
         const double *bvk = bvals + bs;
@@ -734,30 +843,25 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
                     ++ii;
                 }
             }
-            int32_t r[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) r[u] = ark[iu[u]];
-            uint32_t rp[U], col[U];
+            uint64_t en[U];
+            uint32_t col[U];
             double av[U], bvv[U];
-            RowTab rt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t jb = ju[u] < lastb ? ju[u] : lastb;  // padding slots read the run's last B entry
-                rp[u] = rpk[iu[u]];
+                en[u] = enk[iu[u]];
                 av[u] = avk[iu[u]];
                 col[u] = (uint32_t)bck[jb];
                 bvv[u] = bvk[jb];
-                rt[u] = rowtab[r[u]];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (on[u]) {
-                    const int64_t slot = rt[u].base - slot0 + (int64_t)rp[u] + ju[u];
+                    const int64_t slot = (int64_t)(en[u] & kEntSlotMask) - slot0 + ju[u];
                     const bool real = ju[u] <= lastb;
-                    const uint32_t key = real ? ((rt[u].rl << cb) | col[u]) : kSentinel;
+                    const uint32_t key = real ? (((uint32_t)(en[u] >> kEntSlotBits) << cb) | col[u]) : kSentinel;
                     if ((uint64_t)slot < (uint64_t)flop) {
-                        keys[slot] = key;
-                        vals[slot] = real ? (VT)(av[u] * bvv[u]) : (VT)0;
+                        tup.put(slot, key, real ? (VT)(av[u] * bvv[u]) : (VT)0);
                     } else {
                         atomic_or_agent(err, (uint32_t)kErrBinOverflow);
                     }
@@ -771,8 +875,8 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
 
 template <int W, class VT>
 __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
-    expand_body<W, VT>(a.F, a.kstart, a.acp, a.astart, a.brp, a.ari, a.runpos, a.rowtab, a.av, a.bci, a.bv, a.keys,
-                       (VT *)a.vals, a.err, a.cb, a.flop, a.slot0, a.align, nchunks, a.K);
+    expand_body<W, VT>(a.F, a.kstart, a.acp, a.astart, a.brp, a.ent, a.av, a.bci, a.bv,
+                       TupleArr<VT>(a.keys, a.vals), a.err, a.cb, a.flop, a.slot0, a.align, nchunks, a.K);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,7 +889,8 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
 struct CountArgs {
     const int32_t *binrow0;
     const int64_t *binoff;
-    const uint32_t *keys;
+    const uint32_t *keys;  // key of slot i at keys[i * kstride]
+    int kstride;           // 1: FP64 key array; 2: FP32c {key, value} words
     int cb;
     uint32_t *rownnz;
     uint32_t *err;
@@ -825,7 +930,8 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
         for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 - a.row_base + x] = 0;
         return;
     }
-    const uint32_t *gk = a.keys + toff;
+    const int ks = a.kstride;
+    const uint32_t *gk = a.keys + toff * ks;
     const int cb = a.cb;
     constexpr int IPT = TMAX / BLOCK;
     uint32_t kr[IPT];
@@ -834,7 +940,7 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = i * BLOCK + threadIdx.x;
-        kr[i] = gk[p < N ? p : N - 1];
+        kr[i] = gk[(int64_t)(p < N ? p : N - 1) * ks];
     }
     for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
     __syncthreads();
@@ -978,10 +1084,20 @@ struct SegRowPtrDst : NoSide {
 // slot numbers while the values wait in registers; the values are then
 // parked in LDS by slot.  Equal keys are summed in sorted order by the first
 // tuple of each run (Section 3.5's merge) and written at their final place
-// in C, whose row pointers the count pass and the row scan have already
-// produced.  A bin in which at most half of the slots hold distinct keys
-// (the count is C's row-pointer difference) first sums equal keys in an LDS
-// hash table and sorts only the distinct keys.
+// in C.
+//
+// ConvertCSR (Algorithm 2's last step) is fused in: bins take tickets in
+// launch order; once a bin knows how many entries of C it holds (its
+// distinct keys), it publishes that count, and a decoupled look-back over
+// the earlier bins' counts gives the entries of C before it.  The bin then
+// writes its entries and its rows' pointers at their final places.  (The
+// virtual rows of wide rows instead get their row pointers from a count
+// pass and a scan before the sort: `fused` = 0.)
+//
+// Repeated keys.  A bin whose keys crowd the sort's buckets first sums
+// equal keys in an LDS hash table (in double) and sorts only the distinct
+// keys, if at most half of the tile's slots are needed; with given row
+// pointers the trigger is at most half as many entries of C as tuples.
 //
 // Ordering.  Keys are (row in bin) << cb | column.  The default path is a
 // one-pass bucket sort: bucket = (key - min) >> s with NB buckets, counted
@@ -998,7 +1114,7 @@ struct SortArgs {
     const void *vals;
     int cb;
     uint32_t *err;
-    const int64_t *rowptr;
+    int64_t *rowptr;  // single product: C's row pointers, indexed by row - row_base
     int32_t *colidx;
     void *cvals;
     int64_t capacity;
@@ -1010,9 +1126,16 @@ struct SortArgs {
     int64_t bin0;           // first bin of the launch
     int64_t slot0;          // slot of the launch's first tuple in `keys` / `vals`
     int64_t row_base;       // rowptr is indexed by row - row_base
-    const uint64_t *nbins;  // if set, blocks at or past *nbins exit
+    const uint64_t *nbins;  // if set, blocks at or past *nbins exit (unfused only)
     int vshift;             // virtual rows of wide rows: column = (row & vmask) << vshift | key column
     uint32_t vmask;
+    // fused ConvertCSR
+    int fused;                   // 1: the launch writes C's row pointers itself
+    uint32_t *ticket;            // bin order (zeroed)
+    uint64_t *status;            // look-back words, one per bin of the launch (zeroed)
+    const uint32_t *bignnz;      // rounds: entries of C of each wide row, indexed by row - row_base
+    const int64_t *rowptr_base;  // entries of C before the launch's first row (null: none)
+    int64_t rows_end;            // single product: one past the launch's last row
 };
 
 template <class VT>
@@ -1068,6 +1191,42 @@ __device__ __forceinline__ Merge<float> shfl_up_merge(const Merge<float> &x, int
     r.s = __shfl_up(x.s, (unsigned)d, kWave);
     r.c = __shfl_up(x.c, (unsigned)d, kWave);
     return r;
+}
+
+// Loads a bin's N >= 1 tuples (slots [toff, toff + N) of a TupleArr<VT>
+// layout) into registers, tuple p = w * 64 * IPT + i * 64 + lane in rk[i],
+// rv[i]; past N the key is the sentinel.  Every load is issued before any
+// is used: FP64 keys first, so the key phases that follow wait only for them
+// while the values are still arriving; FP32c loads each {key, value} word
+// once.
+template <int BLOCK, int TMAX, class VT>
+__device__ __forceinline__ void load_bin(const uint32_t *keys, const void *vals, int64_t toff, int N,
+                                         uint32_t (&rk)[TMAX / BLOCK], VT (&rv)[TMAX / BLOCK]) {
+    constexpr int IPT = TMAX / BLOCK;
+    const int base = (int)(threadIdx.x / kWave) * kWave * IPT + (int)lane_id();
+    if constexpr (sizeof(VT) == 8) {
+        const uint32_t *gk = keys + toff;
+        const VT *gv = (const VT *)vals + toff;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int p = base + i * kWave;
+            rk[i] = p < N ? gk[p] : kSentinel;
+        }
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int p = base + i * kWave;
+            rv[i] = gv[p < N ? p : N - 1];  // in range for every lane (N >= 1); used only for p < N
+        }
+    } else {
+        const uint2 *gt = (const uint2 *)keys + toff;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int p = base + i * kWave;
+            const uint2 t = gt[p < N ? p : N - 1];
+            rk[i] = p < N ? t.x : kSentinel;
+            rv[i] = __uint_as_float(t.y);
+        }
+    }
 }
 
 constexpr uint32_t kBucketLimit = 40;
@@ -1135,25 +1294,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2
         base = a.rowptr[row0 - a.row_base];
         bend = a.rowptr[row0 + nrows - a.row_base];
     }
-    const uint32_t *gk = a.keys + toff;
-    const VT *gvb = (const VT *)a.vals + toff;
     // padding slots (sentinel keys) are left out of the sort; they are
     // counted so that the sorted tuples occupy [0, Nr)
     uint32_t rk[IPT];
     VT rv[IPT];
     uint32_t kmin = 0xffffffffu, kmax = 0, nreal = 0;
-    // every load is issued before any is used: keys first, so the key
-    // phases below wait only for them while the values are still arriving
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-        rk[i] = p < N ? gk[p] : kSentinel;
-    }
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
-        rv[i] = gvb[p < N ? p : N - 1];  // in range for every lane (N >= 1); parked only for p < N
-    }
+    load_bin<BLOCK, TMAX, VT>(a.keys, a.vals, toff, N, rk, rv);
     // Bins whose keys repeat (at most half of the slots hold
     // distinct keys; that count is known from C's row pointers): equal keys
     // are first summed in an LDS hash table, in double, and only the

@@ -15,6 +15,7 @@
 
 #include "pb_big.h"
 #include "pb_kernels.h"
+#include "pb_sort_fused.h"
 
 using namespace pb;
 
@@ -178,13 +179,16 @@ int col_bits(int64_t n) {
 }
 
 pb_status resolve_tune(const pb_tune *t, int default_tile, int *T, int *chunk, int64_t *round_tuples, int *align,
-                       int *rowcount) {
+                       int *rowcount, int *convert) {
     *T = default_tile;
     *chunk = kDefaultChunk;
     *round_tuples = 0;
     *align = 0;
     *rowcount = 0;
+    *convert = 1;
     if (!t) return PB_OK;
+    if (t->convert < 0 || t->convert > 2) return fail(PB_ERR_ARG, "convert must be 0 (auto), 1 or 2");
+    *convert = t->convert ? t->convert : 1;
     if (t->row_count < 0 || t->row_count > 2) return fail(PB_ERR_ARG, "row_count must be 0 (auto), 1 or 2");
     *rowcount = t->row_count;
     if (t->run_align != 0 && t->run_align != 1 && t->run_align != 4 && t->run_align != 8)
@@ -218,12 +222,13 @@ struct pb_plan {
     int T = kDefaultTile, chunk = kDefaultChunk, cb = 0;
     int align = 1;  // run alignment in tuple slots
     int rowcount = 1;  // per-row flop: 1 device atomics, 2 row buckets
+    int convert = 1;   // ConvertCSR: 1 count pass + row scan, 2 fused into the sort
     // symbolic workspace tables
     SymInfo *info = nullptr;
     int64_t *F = nullptr;
     uint64_t *R = nullptr;
     RowTab *rowtab = nullptr;
-    uint32_t *runpos = nullptr;
+    uint64_t *ent = nullptr;  // per A entry: run destination (ent_pack)
     int32_t *binrow0 = nullptr;
     int64_t *binoff = nullptr;
     // batch: packed inputs and problem tables (in the symbolic workspace)
@@ -236,6 +241,8 @@ struct pb_plan {
     std::vector<int64_t> prob_flop;  // per-problem multiplications
     void *pinned = nullptr;          // host staging for descriptor uploads
     size_t pinned_bytes = 0;
+    hipEvent_t staged = nullptr;     // recorded after a batched call's uploads from the staging area
+    bool staged_pending = false;
     // host facts
     SymInfo h{};
     int64_t nchunks = 0;
@@ -254,6 +261,7 @@ struct pb_plan {
     };
     std::vector<Round> rounds;
     ~pb_plan() {
+        if (staged) (void)hipEventDestroy(staged);
         if (pinned) (void)hipHostFree(pinned);
     }
 };
@@ -267,7 +275,8 @@ struct SymLayout {
     uint64_t *R;
     int64_t *F;
     RowTab *rowtab;
-    uint32_t *runpos;
+    uint32_t *runpos;  // device atomics only: each entry's run offset in its row
+    uint64_t *ent;
     int32_t *binrow0;
     int64_t *binoff;
     // row buckets (rowcount 2)
@@ -277,6 +286,7 @@ struct SymLayout {
     uint64_t *gflop;
     uint32_t *rec, *roff;
     uint32_t *posof;
+    uint64_t *entrec;
     int nbkt, ngrp;
     int64_t epw, cpw;
     // batch only
@@ -336,7 +346,8 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
     L.zero_bytes = cv.mark();
     L.F = cv.take<int64_t>(k + 1);
     L.rowtab = cv.take<RowTab>(m);
-    L.runpos = cv.take<uint32_t>(nnza);
+    L.runpos = cv.take<uint32_t>(rowcount == 2 ? 0 : nnza);
+    L.ent = cv.take<uint64_t>(nnza);
     L.binrow0 = cv.take<int32_t>(m + 1);
     L.binoff = cv.take<int64_t>(m + 1);
     if (rowcount == 2) {
@@ -346,6 +357,7 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
         L.rec = cv.take<uint32_t>(nnza);
         L.roff = cv.take<uint32_t>(nnza);
         L.posof = cv.take<uint32_t>(nnza);
+        L.entrec = cv.take<uint64_t>(nnza);
     }
     if (count > 1) {
         L.pdesc = cv.take<ProbDesc>(count);
@@ -362,8 +374,8 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
 }
 
 struct NumLayout {
-    uint32_t *ticket, *err;
-    uint64_t *status;
+    uint32_t *ticket, *err, *sticket;
+    uint64_t *status, *sstatus;
     int32_t *kstart;
     uint32_t *rownnz;
     OutDesc *outs;
@@ -375,17 +387,24 @@ struct NumLayout {
 NumLayout num_layout(void *base, const pb_plan *p) {
     Carver cv(base);
     NumLayout L{};
-    L.ticket = cv.take<uint32_t>(2);
+    L.ticket = cv.take<uint32_t>(3);
     L.err = L.ticket + 1;
+    L.sticket = L.ticket + 2;
     L.status = cv.take<uint64_t>(ceil_div(p->m, kScanTile) + 1);
+    L.sstatus = cv.take<uint64_t>((int64_t)p->h.nbins + 1);
     L.zero_bytes = cv.mark();
     L.kstart = cv.take<int32_t>(p->nchunks + 1);
     L.rownnz = cv.take<uint32_t>(p->m);
     L.outs = p->count > 1 ? cv.take<OutDesc>(p->count) : nullptr;
     const int64_t flop = (int64_t)p->h.slots;
-    L.keys = cv.take<uint32_t>(flop);
-    if (p->prec == PB_F64) L.vals = cv.take<double>(flop);
-    else L.vals = cv.take<float>(flop);
+    // tuples (TupleArr): FP64 keys and values apart, FP32c {key, value} words
+    if (p->prec == PB_F64) {
+        L.keys = cv.take<uint32_t>(flop);
+        L.vals = cv.take<double>(flop);
+    } else {
+        L.keys = (uint32_t *)cv.take<uint2>(flop);
+        L.vals = nullptr;
+    }
     L.total = cv.mark();
     return L;
 }
@@ -411,6 +430,22 @@ pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *t
     return PB_OK;
 }
 
+// Row scan (each row's first slot) and bin cut over the per-row slot counts.
+pb_status run_row_bins(pb_plan *p, const SymLayout &L, hipStream_t st) {
+    const int64_t m = p->m;
+    if (m <= 0) return PB_OK;
+    PB_TRY(launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(p->T / 2), L.info}, L.stR,
+                              &L.tickets[1], &L.info->err, st, "row scan"));
+    PB_TRY(launch_scan<BinOp>(
+        m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count, -1},
+        BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2],
+        &L.info->err, st, "bin scan"));
+    hipLaunchKernelGGL(k_bin_max, dim3((unsigned)std::min<int64_t>(ceil_div(m, 256), 512)), dim3(256), 0, st, L.binoff,
+                       m, L.info);
+    PB_LAUNCHED("largest bin");
+    return PB_OK;
+}
+
 // Symbolic kernels on device arrays (the product's, or the packed batch's):
 // flop scan, per-row flop with run offsets, row scan, bin cut.
 pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const int32_t *ari, const int64_t *brp,
@@ -420,9 +455,28 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
         PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp, p->align}, ColFlopDst{{}, L.F, k, L.info}, L.stF,
                                   &L.tickets[0], &L.info->err, st, "flop scan"));
         if (p->rowcount == 2) {
-            const RowBucketArgs ra{k,      p->nnzA, acp,      brp,    ari,     p->align, L.epw,    L.nbkt, L.ngrp,
-                                   L.cpw,  L.kstart, L.hist, L.gflop, L.rec,  L.roff,   L.posof,  L.runpos, L.R,
-                                   L.info};
+            RowBucketArgs ra{};
+            ra.K = k;
+            ra.nnz = p->nnzA;
+            ra.acp = acp;
+            ra.brp = brp;
+            ra.ari = ari;
+            ra.align = p->align;
+            ra.epw = L.epw;
+            ra.nbkt = L.nbkt;
+            ra.ngrp = L.ngrp;
+            ra.cpw = L.cpw;
+            ra.kstart = L.kstart;
+            ra.hist = L.hist;
+            ra.gflop = L.gflop;
+            ra.rec = L.rec;
+            ra.roff = L.roff;
+            ra.posof = L.posof;
+            ra.rowflop = L.R;
+            ra.info = L.info;
+            ra.rowtab = L.rowtab;
+            ra.entrec = L.entrec;
+            ra.ent = L.ent;
             const int64_t nh = (int64_t)L.nbkt * L.ngrp;
             const size_t lds = (size_t)L.nbkt * sizeof(uint32_t);
             const dim3 grid((unsigned)L.ngrp), block(kBucketBlock);
@@ -434,46 +488,56 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
             PB_LAUNCHED("bucket scatter");
             hipLaunchKernelGGL(k_bucket_count<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
             PB_LAUNCHED("bucket count");
+            PB_TRY(run_row_bins(p, L, st));
+            hipLaunchKernelGGL(k_bucket_dest<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
+            PB_LAUNCHED("bucket destinations");
             hipLaunchKernelGGL(k_bucket_offsets<kBucketBlock>, grid, block, 0, st, ra);
             PB_LAUNCHED("bucket offsets");
         } else {
             hipLaunchKernelGGL(k_rowflop<256>, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, st, k, acp, ari, brp,
                                p->align, L.R, L.runpos, L.info);
             PB_LAUNCHED("rowflop");
+            PB_TRY(run_row_bins(p, L, st));
+            if (p->nnzA > 0) {
+                hipLaunchKernelGGL(k_entry_dest, dim3((unsigned)ceil_div(p->nnzA, 256)), dim3(256), 0, st, p->nnzA,
+                                   ari, L.runpos, L.rowtab, L.ent);
+                PB_LAUNCHED("entry destinations");
+            }
         }
     } else {
         PB_TRY(fill_zero(L.F, sizeof(int64_t), st));
-    }
-    if (m > 0) {
-        PB_TRY(launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(p->T / 2), L.info}, L.stR,
-                                  &L.tickets[1], &L.info->err, st, "row scan"));
-        PB_TRY(launch_scan<BinOp>(
-            m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count, -1},
-            BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2],
-            &L.info->err, st, "bin scan"));
+        PB_TRY(run_row_bins(p, L, st));
     }
     return PB_OK;
 }
 
 // Sort + compress launch for `nbins` bins of at most T tuples (T picks the
 // kernel shape).
+#define PB_SORT_LAUNCH(KERNEL)                                                                                   \
+    do {                                                                                                         \
+        if (T <= kSortTmaxSmall) {                                                                               \
+            if (f64)                                                                                             \
+                hipLaunchKernelGGL((KERNEL<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins),     \
+                                   dim3(kSortBlockSmall), 0, st, sa);                                            \
+            else                                                                                                 \
+                hipLaunchKernelGGL((KERNEL<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins),      \
+                                   dim3(kSortBlockSmall), 0, st, sa);                                            \
+        } else {                                                                                                 \
+            if (f64)                                                                                             \
+                hipLaunchKernelGGL((KERNEL<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins), dim3(kSortBlock), \
+                                   0, st, sa);                                                                   \
+            else                                                                                                 \
+                hipLaunchKernelGGL((KERNEL<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins), dim3(kSortBlock), \
+                                   0, st, sa);                                                                   \
+        }                                                                                                        \
+    } while (0)
+
+// Sort + compress launch for `nbins` bins of at most T tuples (T picks the
+// kernel shape; sa.fused the ConvertCSR mode).
 pb_status launch_sort(const pb_plan *p, int64_t T, const SortArgs &sa, int64_t nbins, hipStream_t st) {
     const bool f64 = p->prec == PB_F64;
-    if (T <= kSortTmaxSmall) {
-        if (f64)
-            hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins),
-                               dim3(kSortBlockSmall), 0, st, sa);
-        else
-            hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins),
-                               dim3(kSortBlockSmall), 0, st, sa);
-    } else {
-        if (f64)
-            hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins),
-                               dim3(kSortBlock), 0, st, sa);
-        else
-            hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins),
-                               dim3(kSortBlock), 0, st, sa);
-    }
+    if (sa.fused) PB_SORT_LAUNCH(k_sort_compress_fused);
+    else PB_SORT_LAUNCH(k_sort_compress);
     PB_LAUNCHED("sort+compress");
     return PB_OK;
 }
@@ -485,10 +549,10 @@ pb_status ensure_pinned(pb_plan *p, size_t bytes);
 // first; the wide-row tables (bigs, bige, cpre, bigr) are one block, in the
 // order of the pinned staging copy.
 struct RoundLayout {
-    uint32_t *tickets;  // [0] rows, [1] columns, [2] virtual rows, [3] virtual bins
+    uint32_t *tickets;  // [0] rows, [1] columns, [2] virtual rows, [3] virtual bins, [5] sorted bins
     uint32_t *err;
     SymInfo *rinfo, *vinfo;
-    uint64_t *st_rows, *st_cols, *st_v, *st_vb;
+    uint64_t *st_rows, *st_cols, *st_v, *st_vb, *st_sort;
     uint32_t *cnt_v, *cur_v;
     size_t zero_bytes;
     int64_t *astart;
@@ -529,7 +593,7 @@ RoundLayout round_layout(void *base, const pb_plan *p, const pb_plan::Round &rd)
     const bool partial = rd.r0 > 0 || rd.r1 < p->m;
     const int64_t nrows = rd.r1 - rd.r0;
     const int vb = p->prec == PB_F64 ? 8 : 4;
-    L.tickets = cv.take<uint32_t>(5);
+    L.tickets = cv.take<uint32_t>(6);
     L.err = L.tickets + 4;
     L.rinfo = cv.take<SymInfo>(1);
     L.vinfo = cv.take<SymInfo>(1);
@@ -537,6 +601,7 @@ RoundLayout round_layout(void *base, const pb_plan *p, const pb_plan::Round &rd)
     L.st_cols = cv.take<uint64_t>(partial ? ceil_div(p->k, kScanTile) + 1 : 0);
     L.st_v = cv.take<uint64_t>(ceil_div(rd.nvirt, kScanTile) + 1);
     L.st_vb = cv.take<uint64_t>(ceil_div(rd.nvirt, kScanTile) + 1);
+    L.st_sort = cv.take<uint64_t>(rd.b1 - rd.b0 + 1);
     L.cnt_v = cv.take<uint32_t>(rd.nvirt);
     L.cur_v = cv.take<uint32_t>(rd.nvirt);
     L.zero_bytes = cv.mark();
@@ -561,10 +626,18 @@ RoundLayout round_layout(void *base, const pb_plan *p, const pb_plan::Round &rd)
     L.dense = cv.take<int32_t>(rd.ndense);
     L.rownnz_v = cv.take<uint32_t>(rd.nvirt);
     L.rowptr_v = cv.take<int64_t>(rd.nbig ? rd.nvirt + 1 : 0);
-    L.keys2 = cv.take<uint32_t>(rd.bigflop);
-    L.vals2 = cv.take<char>(rd.bigflop * vb);
-    L.keys = cv.take<uint32_t>(rd.flop);
-    L.vals = cv.take<char>(rd.flop * vb);
+    // tuples (TupleArr): FP64 keys and values apart, FP32c {key, value} words
+    if (vb == 8) {
+        L.keys2 = cv.take<uint32_t>(rd.bigflop);
+        L.vals2 = cv.take<double>(rd.bigflop);
+        L.keys = cv.take<uint32_t>(rd.flop);
+        L.vals = cv.take<double>(rd.flop);
+    } else {
+        L.keys2 = (uint32_t *)cv.take<uint2>(rd.bigflop);
+        L.vals2 = nullptr;
+        L.keys = (uint32_t *)cv.take<uint2>(rd.flop);
+        L.vals = nullptr;
+    }
     L.total = cv.mark();
     return L;
 }
@@ -699,8 +772,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(nchunks + 1, 256)), dim3(256), 0, st, nchunks,
                            (int64_t)p->chunk, K, F, L.kstart);
         PB_LAUNCHED("chunk start");
-        ExpandArgs ea{rd.flop, K, F, L.kstart, A->ptr, A->idx, A->val, B->ptr, B->idx, B->val, p->runpos,
-                      p->rowtab, L.keys, L.vals, p->cb, L.err, astart, rd.slot0, p->align};
+        ExpandArgs ea{rd.flop, K, F, L.kstart, A->ptr, A->val, B->ptr, B->idx, B->val, p->ent,
+                      L.keys, L.vals, p->cb, L.err, astart, rd.slot0, p->align};
         const unsigned grid = (unsigned)ceil_div(nchunks, 4);
         switch (p->chunk) {
             case 256:
@@ -724,7 +797,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
     }
     const int64_t nb = rd.b1 - rd.b0;
     const int nwin = 1 << p->lognwin;
-    BigArgs ba{rd.nbig, p->lognwin, p->wbits, p->cb, L.bigs, L.bige, L.cpre, L.keys, L.vals, L.chist, L.cnt_v,
+    const int kstride = f64 ? 1 : 2;  // TupleArr key stride
+    BigArgs ba{rd.nbig, p->lognwin, p->wbits, p->cb, L.bigs, L.bige, L.cpre, L.keys, L.vals, kstride, L.chist, L.cnt_v,
                L.cur_v, L.Rv, L.vrowtab, L.keys2, L.vals2, rd.bigflop, L.err};
     if (rd.nbig) {
         ProfScope ps(st, 4);
@@ -744,10 +818,16 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
     DenseArgs da{L.dense, &L.vinfo->noversize, L.Rv, L.keys2, L.vals2, p->wbits, p->lognwin, L.rownnz_v,
                  L.rowptr_v, colidx, cval, capacity, L.err};
     const unsigned dgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rd.ndense, 2048));
+    // With ConvertCSR fused into the sort, the main bins count their own
+    // entries; a wide row's count (the sum over its column windows) must be
+    // known before the main sort, and its windows' row pointers come from
+    // its row pointer after it.
+    const bool fused = p->convert != 1;
     {
         ProfScope ps(st, 3);
-        if (nb > 0) {
-            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err, p->T, rd.b0, rd.slot0, rd.r0, nullptr};
+        if (nb > 0 && !fused) {
+            CountArgs ca{p->binrow0, p->binoff, L.keys, kstride, p->cb, L.rownnz, L.err, p->T, rd.b0, rd.slot0, rd.r0,
+                         nullptr};
             if (p->T <= kSortTmaxSmall)
                 hipLaunchKernelGGL((k_row_nnz<kCountBlockSmall, kSortTmaxSmall>), dim3((unsigned)nb),
                                    dim3(kCountBlockSmall), 0, st, ca);
@@ -757,7 +837,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
             PB_LAUNCHED("row counts");
         }
         if (rd.nbig) {
-            CountArgs cv{L.vbinrow0, L.vbinoff, L.keys2, p->wbits, L.rownnz_v, L.err, p->Tv, 0, 0, 0, &L.vinfo->nbins};
+            CountArgs cv{L.vbinrow0, L.vbinoff, L.keys2, kstride, p->wbits, L.rownnz_v, L.err, p->Tv, 0, 0, 0,
+                         &L.vinfo->nbins};
             if (p->Tv <= kSortTmaxSmall)
                 hipLaunchKernelGGL((k_row_nnz<kCountBlockSmall, kSortTmaxSmall>), dim3((unsigned)rd.nvbins),
                                    dim3(kCountBlockSmall), 0, st, cv);
@@ -772,25 +853,57 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
                                p->lognwin, L.bigr, rd.r0, L.rownnz_v, L.rownnz);
             PB_LAUNCHED("wide-row sums");
         }
-        if (nrows > 0)
+        if (!fused && nrows > 0)
             PB_TRY(launch_scan<SumOp>(nrows, RowNnzSrc{L.rownnz}, RowPtrDst{{}, rowptr_out, nrows, rowptr_base},
                                       L.st_rows, &L.tickets[0], L.err, st, "row pointer scan"));
-        if (rd.nbig) {
-            hipLaunchKernelGGL(k_big_rowptr, dim3((unsigned)ceil_div(rd.nbig, 4)), dim3(256), 0, st, rd.nbig,
-                               p->lognwin, L.bigr, rd.r0, rowptr_out, L.rownnz_v, L.rowptr_v);
-            PB_LAUNCHED("virtual row pointers");
-        }
     }
     {
         ProfScope ps(st, 2);
         if (nb > 0) {
-            SortArgs sa{p->binrow0, p->binoff, L.keys, L.vals, p->cb, L.err, rowptr_out, colidx, cval, capacity,
-                        nullptr, nullptr, 1, p->T, rd.b0, rd.slot0, rd.r0, nullptr, 0, 0};
+            SortArgs sa{};
+            sa.binrow0 = p->binrow0;
+            sa.binoff = p->binoff;
+            sa.keys = L.keys;
+            sa.vals = L.vals;
+            sa.cb = p->cb;
+            sa.err = L.err;
+            sa.rowptr = rowptr_out;
+            sa.colidx = colidx;
+            sa.cvals = cval;
+            sa.capacity = capacity;
+            sa.nprob = 1;
+            sa.T = p->T;
+            sa.bin0 = rd.b0;
+            sa.slot0 = rd.slot0;
+            sa.row_base = rd.r0;
+            sa.fused = fused ? 1 : 0;
+            sa.ticket = &L.tickets[5];
+            sa.status = L.st_sort;
+            sa.bignnz = L.rownnz;
+            sa.rowptr_base = rowptr_base;
+            sa.rows_end = rd.r1;
             PB_TRY(launch_sort(p, p->T, sa, nb, st));
         }
         if (rd.nbig) {
-            SortArgs sv{L.vbinrow0, L.vbinoff, L.keys2, L.vals2, p->wbits, L.err, L.rowptr_v, colidx, cval, capacity,
-                        nullptr, nullptr, 1, p->Tv, 0, 0, 0, &L.vinfo->nbins, p->wbits, (uint32_t)(nwin - 1)};
+            hipLaunchKernelGGL(k_big_rowptr, dim3((unsigned)ceil_div(rd.nbig, 4)), dim3(256), 0, st, rd.nbig,
+                               p->lognwin, L.bigr, rd.r0, rowptr_out, L.rownnz_v, L.rowptr_v);
+            PB_LAUNCHED("virtual row pointers");
+            SortArgs sv{};
+            sv.binrow0 = L.vbinrow0;
+            sv.binoff = L.vbinoff;
+            sv.keys = L.keys2;
+            sv.vals = L.vals2;
+            sv.cb = p->wbits;
+            sv.err = L.err;
+            sv.rowptr = L.rowptr_v;
+            sv.colidx = colidx;
+            sv.cvals = cval;
+            sv.capacity = capacity;
+            sv.nprob = 1;
+            sv.T = p->Tv;
+            sv.nbins = &L.vinfo->nbins;
+            sv.vshift = p->wbits;
+            sv.vmask = (uint32_t)(nwin - 1);
             PB_TRY(launch_sort(p, p->Tv, sv, rd.nvbins, st));
             if (f64) hipLaunchKernelGGL((k_dense<512, double, true>), dim3(dgrid), dim3(512), 0, st, da);
             else hipLaunchKernelGGL((k_dense<512, float, true>), dim3(dgrid), dim3(512), 0, st, da);
@@ -805,6 +918,9 @@ pb_status finish_symbolic(pb_plan *p, hipStream_t st) {
     PB_HIP(hipStreamSynchronize(st));
     if (p->h.err) return fail(PB_ERR_INTERNAL, "symbolic device error 0x%x", p->h.err);
     if (p->m == 0) p->h.nbins = 0;
+    if (p->h.slots > kEntSlotMask)
+        return fail(PB_ERR_UNSUPPORTED, "the product expands to %llu tuple slots; at most 2^40 - 1 are supported",
+                    (unsigned long long)p->h.slots);
     if (p->h.maxrow >= ((uint64_t)1 << 32))
         return fail(PB_ERR_UNSUPPORTED, "a row of C expands to %llu tuples; at most 2^32 - 1 are supported",
                     (unsigned long long)p->h.maxrow);
@@ -831,8 +947,8 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
         hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)ceil_div(p->nchunks + 1, 256)), dim3(256), 0, st, p->nchunks,
                            (int64_t)p->chunk, p->k, p->F, L.kstart);
         PB_LAUNCHED("chunk start");
-        ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, ari, av, brp, bci, bv, p->runpos, p->rowtab, L.keys, L.vals,
-                      p->cb, L.err, nullptr, 0, p->align};
+        ExpandArgs ea{flop, p->k, p->F, L.kstart, acp, av, brp, bci, bv, p->ent, L.keys, L.vals, p->cb, L.err,
+                      nullptr, 0, p->align};
         ProfScope ps(st, 1);
         const unsigned grid = (unsigned)ceil_div(p->nchunks, 4);
         switch (p->chunk) {
@@ -856,9 +972,10 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
         PB_LAUNCHED("expand");
     }
     if (nbins > 0) {
-        {
+        const bool fused = p->convert != 1;
+        if (!fused) {
             ProfScope ps(st, 3);
-            CountArgs ca{p->binrow0, p->binoff, L.keys, p->cb, L.rownnz, L.err, p->T, 0, 0, 0, nullptr};
+            CountArgs ca{p->binrow0, p->binoff, L.keys, f64 ? 1 : 2, p->cb, L.rownnz, L.err, p->T, 0, 0, 0, nullptr};
             if (p->T <= kSortTmaxSmall)
                 hipLaunchKernelGGL((k_row_nnz<kCountBlockSmall, kSortTmaxSmall>), dim3((unsigned)nbins),
                                    dim3(kCountBlockSmall), 0, st, ca);
@@ -875,43 +992,31 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
                                           L.err, st, "row pointer scan"));
             }
         }
-        SortArgs sa{p->binrow0,
-                    p->binoff,
-                    L.keys,
-                    L.vals,
-                    p->cb,
-                    L.err,
-                    batch ? nullptr : C->rowptr,
-                    batch ? nullptr : C->colidx,
-                    batch ? nullptr : C->val,
-                    batch ? 0 : C->capacity,
-                    batch ? L.outs : nullptr,
-                    batch ? p->prob_row0 : nullptr,
-                    p->count,
-                    p->T,
-                    0,
-                    0,
-                    0,
-                    nullptr,
-                    0,
-                    0};
-        ProfScope ps(st, 2);
-        if (p->T <= kSortTmaxSmall) {
-            if (f64)
-                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, double>), dim3((unsigned)nbins),
-                                   dim3(kSortBlockSmall), 0, st, sa);
-            else
-                hipLaunchKernelGGL((k_sort_compress<kSortBlockSmall, kSortTmaxSmall, float>), dim3((unsigned)nbins),
-                                   dim3(kSortBlockSmall), 0, st, sa);
+        SortArgs sa{};
+        sa.binrow0 = p->binrow0;
+        sa.binoff = p->binoff;
+        sa.keys = L.keys;
+        sa.vals = L.vals;
+        sa.cb = p->cb;
+        sa.err = L.err;
+        if (batch) {
+            sa.outs = L.outs;
+            sa.prob_row0 = p->prob_row0;
+            sa.nprob = p->count;
         } else {
-            if (f64)
-                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, double>), dim3((unsigned)nbins),
-                                   dim3(kSortBlock), 0, st, sa);
-            else
-                hipLaunchKernelGGL((k_sort_compress<kSortBlock, kSortTmax, float>), dim3((unsigned)nbins),
-                                   dim3(kSortBlock), 0, st, sa);
+            sa.rowptr = C->rowptr;
+            sa.colidx = C->colidx;
+            sa.cvals = C->val;
+            sa.capacity = C->capacity;
+            sa.nprob = 1;
         }
-        PB_LAUNCHED("sort+compress");
+        sa.T = p->T;
+        sa.rows_end = p->m;
+        sa.fused = fused ? 1 : 0;
+        sa.ticket = L.sticket;
+        sa.status = L.sstatus;
+        ProfScope ps(st, 2);
+        PB_TRY(launch_sort(p, p->T, sa, nbins, st));
     }
     return PB_OK;
 }
@@ -1074,9 +1179,9 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
         return fail(PB_ERR_SHAPE, "A.ncols (%lld) != B.nrows (%lld)", (long long)A->ncols, (long long)B->nrows);
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk, align, rowreq;
+    int T, chunk, align, rowreq, convert;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, kDefaultTile, &T, &chunk, &round_tuples, &align, &rowreq));
+    PB_TRY(resolve_tune(tune, kDefaultTile, &T, &chunk, &round_tuples, &align, &rowreq, &convert));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
     const int rowcount = pick_rowcount(rowreq, m, k, A->nnz);
     if (rowcount < 0)
@@ -1111,6 +1216,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->chunk = chunk;
     p->cb = cb;
     p->round_tuples = round_tuples;
+    p->convert = convert;
     // FP64 runs padded to 4 slots (whole 32-byte sectors of values) when B's
     // rows are long enough on average for the padding to cost little next to
     // the partial-sector writes it avoids (measured: ER 2^20 d=16 step -3%;
@@ -1121,7 +1227,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->F = L.F;
     p->R = L.R;
     p->rowtab = L.rowtab;
-    p->runpos = L.runpos;
+    p->ent = L.ent;
     p->binrow0 = L.binrow0;
     p->binoff = L.binoff;
     pb_status rs = fill_zero(sym_ws, L.zero_bytes, st);
@@ -1288,9 +1394,9 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     PB_TRY(check_batch(count, A, B));
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk, align, rowreq;
+    int T, chunk, align, rowreq, convert;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, kDefaultTileBatched, &T, &chunk, &round_tuples, &align, &rowreq));
+    PB_TRY(resolve_tune(tune, kDefaultTileBatched, &T, &chunk, &round_tuples, &align, &rowreq, &convert));
     std::vector<ProbDesc> hd;
     int64_t m, k, n, nnza, nnzb;
     batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);
@@ -1345,11 +1451,12 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     p->T = T;
     p->chunk = chunk;
     p->cb = cb;
+    p->convert = convert;
     p->info = L.info;
     p->F = L.F;
     p->R = L.R;
     p->rowtab = L.rowtab;
-    p->runpos = L.runpos;
+    p->ent = L.ent;
     p->binrow0 = L.binrow0;
     p->binoff = L.binoff;
     p->pdesc = L.pdesc;
@@ -1421,6 +1528,17 @@ pb_status spgemm_batched(pb_plan *p, int32_t count, const pb_csx *A, const pb_cs
     hipStream_t st = (hipStream_t)hip_stream;
     NumLayout L = num_layout(workspace, p);
     const int32_t cnt = p->count;
+    // The staging area is read by the previous call's uploads, which may
+    // still be queued: wait for them before rewriting it.  Under stream
+    // capture nothing is waited for or recorded; a replay then uploads what
+    // the staging area holds at replay time (the latest call's descriptors).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    PB_HIP(hipStreamIsCapturing(st, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (!capturing && p->staged_pending) {
+        PB_HIP(hipEventSynchronize(p->staged));
+        p->staged_pending = false;
+    }
     // input descriptors (the arrays may have moved since the symbolic step)
     // and output descriptors, through the pinned staging area
     ProbDesc *sd = staged_desc(p);
@@ -1441,6 +1559,11 @@ pb_status spgemm_batched(pb_plan *p, int32_t count, const pb_csx *A, const pb_cs
     }
     PB_HIP(hipMemcpyAsync(p->pdesc, sd, sizeof(ProbDesc) * cnt, hipMemcpyHostToDevice, st));
     PB_HIP(hipMemcpyAsync(L.outs, so, sizeof(OutDesc) * cnt, hipMemcpyHostToDevice, st));
+    if (!capturing) {
+        if (!p->staged) PB_HIP(hipEventCreateWithFlags(&p->staged, hipEventDisableTiming));
+        PB_HIP(hipEventRecord(p->staged, st));
+        p->staged_pending = true;
+    }
     PB_TRY(fill_zero(workspace, L.zero_bytes, st));
     PB_TRY(launch_pack(p, 2, st));
     for (int32_t i = 0; i < count; ++i)
@@ -1477,7 +1600,7 @@ pb_status spgemm_plan_info(const pb_plan *p, pb_plan_info *info) {
     info->run_align = p->align;
     info->row_count = p->rowcount;
     info->nbins = (int64_t)p->h.nbins;
-    info->max_bin_tuples = p->T;
+    info->max_bin_tuples = (int64_t)p->h.maxbin;
     info->max_row_flop = (int64_t)p->h.maxrow;
     info->tile_tuples = p->T;
     info->expand_chunk = p->chunk;

@@ -112,6 +112,7 @@ def test_tune_struct_layout():
     assert B.PbTune.round_tuples.offset == 8
     assert B.PbTune.run_align.offset == 16
     assert B.PbTune.row_count.offset == 20
+    assert B.PbTune.convert.offset == 24
     assert ctypes.sizeof(B.PbPlanInfo) % 8 == 0
 
 

@@ -209,3 +209,35 @@ def test_batch_512_workload_vs_oracle(pb):
                 _compare_rows(c, oracle.spgemm_rows(a, b, rows, nthreads=nth), rows, precision, what)
         del outs
         torch.cuda.empty_cache()
+
+
+def test_back_to_back_calls_into_different_outputs(pb):
+    """Two stream-ordered calls on one plan, each into its own outputs, with
+    no synchronisation between them: the second call's descriptors must not
+    overwrite the first's before the first has uploaded them."""
+    import torch
+
+    _say("two unsynchronised batched calls, different outputs")
+    probs = _uneven_batch(seed=13)[:6]
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    nsym = pb.spgemm_batched_symbolic(pairs)
+    plan = pb.spgemm_batched_symbolic(pairs, sym_ws=torch.empty(nsym, dtype=torch.uint8, device="cuda"))
+    ws = [torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda") for _ in range(2)]
+
+    def outputs():
+        return [(torch.full((a.nrows + 1,), -1, dtype=torch.int64, device="cuda"),
+                 torch.full((max(f, 1),), -1, dtype=torch.int32, device="cuda"),
+                 torch.full((max(f, 1),), float("nan"), dtype=torch.float64, device="cuda"))
+                for (a, _), f in zip(pairs, plan.flops)]
+
+    o1, o2 = outputs(), outputs()
+    torch.cuda.synchronize()
+    pb.spgemm_batched(plan, pairs, ws[0], o1, sync=False)
+    pb.spgemm_batched(plan, pairs, ws[1], o2, sync=False)
+    torch.cuda.synchronize()
+    for outs in (o1, o2):
+        for (a, b), (rp, ci, cv) in zip(probs, outs):
+            ref = _ref(a, b)
+            z = int(rp[-1].item())
+            _check(dict(rowptr=rp.cpu().numpy(), colidx=ci[:z].cpu().numpy(), val=cv[:z].cpu().numpy()), ref, "f64")
+    plan.close()

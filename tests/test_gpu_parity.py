@@ -416,3 +416,32 @@ def test_last_row_of_full_bin_at_last_column(pb, case):
     for precision in ("f64", "f32c"):
         got = _run(pb, a, b, precision, tune={"tile_tuples": tile})
         _compare(got, ref, precision)
+
+
+@pytest.mark.parametrize("case", ["er", "empty_rows", "big_rows"])
+def test_bin_cut_matches_rule(pb, case):
+    """The device's bin count and largest bin equal the bin-cut rule
+    restated on the host (tests/test_bin_cut.py) over the rows' tuple
+    counts (run alignment 1, so a row's slots are its multiplications)."""
+    from test_bin_cut import bin_starts
+
+    _say(f"bin cut vs host rule: {case}")
+    tile = 1024
+    if case == "er":
+        a, b = er_problem(30000, 7, 61, 62)
+    elif case == "empty_rows":
+        a, b = _one_column_pattern(9000, 2, 1 << 20, [[0, 4000], [8999]], [np.arange(300) * 17, [5, 9, 1 << 19]], 3)
+    else:
+        a = random_sparse(900, 400, 0.01, 21, "csc", dense_rows=(5, 6, 400, 899))
+        b = random_sparse(400, 700, 0.0015, 22, "csr")
+    nnzb = np.diff(b.ptr)
+    rowflop = np.bincount(a.idx, weights=np.repeat(nnzb, np.diff(a.ptr)), minlength=a.nrows).astype(np.int64)
+    cb = int(b.ncols - 1).bit_length() if b.ncols > 1 else 0
+    starts = bin_starts(rowflop, tile, 32 - cb)
+    R = np.concatenate([[0], np.cumsum(rowflop)])
+    sizes = R[np.concatenate([starts[1:], [a.nrows]])] - R[starts]
+    info = _plan_info(pb, pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b), "f64",
+                      {"tile_tuples": tile, "run_align": 1})
+    assert info["nbins"] == starts.size
+    assert info["max_bin_tuples"] == int(sizes.max())
+    assert info["max_row_flop"] == int(rowflop.max())
