@@ -397,9 +397,10 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t
     for (int i = threadIdx.x; i < kRowBucketRows && r0 + i < m; i += BLOCK) a.rowflop[r0 + i] = s_cnt[i];
 }
 
-// Pass 4 (after the row scan and the bin cut): one workgroup per bucket
-// holds its rows' first slots and rows-in-bin in LDS and turns every record's
-// run offset into the run's destination word.
+// Pass 4 (after the row scan and the bin cut): the workgroups of a bucket
+// (gridDim.y slices of its records) hold its rows' first slots and
+// rows-in-bin in LDS and turn every record's run offset into the run's
+// destination word.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_dest(RowBucketArgs a, int64_t m) {
     __shared__ uint64_t s_base[kRowBucketRows];
@@ -414,7 +415,10 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_dest(RowBucketArgs a, int64_t 
         }
     }
     __syncthreads();
-    const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
+    const uint32_t q0 = a.hist[b * a.ngrp], q1 = a.hist[(b + 1) * a.ngrp];
+    const uint32_t per = (q1 - q0 + gridDim.y - 1) / gridDim.y;
+    const uint32_t p0 = q0 + per * blockIdx.y;
+    const uint32_t p1 = p0 + per < q1 ? p0 + per : q1;
     constexpr int U = 4;
     for (int64_t p = (int64_t)p0 + threadIdx.x; p < p1; p += (int64_t)BLOCK * U) {
         uint32_t rc[U], off[U];
