@@ -116,7 +116,20 @@ typedef struct {
  *                 and takes the entries before it from the earlier bins by a
  *                 decoupled look-back; measured slower, because each bin
  *                 waits for the counts of the bins before it); 0 = 1.  C is
- *                 the same either way. */
+ *                 the same either way.
+ *   deterministic 1 = bit-identical C on every call with the same inputs and
+ *                 tuning (Section 3.4's bins summed in a fixed order): the
+ *                 runs of a row of C sit in ascending column order of A, the
+ *                 bin sort is stable, and every entry of C is summed one
+ *                 tuple at a time in that order, so an FP64 entry is
+ *                 ((A(i,k1)B(k1,j) + A(i,k2)B(k2,j)) + ...) over ascending k,
+ *                 rounded after every operation.  Costs a per-row ordering
+ *                 pass in the symbolic step and gives up the LDS hash
+ *                 pre-summation and the segmented reduction.  Needs row
+ *                 buckets (see row_count; row_count 1 is PB_ERR_ARG),
+ *                 convert 0 or 1 (2 is PB_ERR_ARG), and no row of C wider than
+ *                 the tile (the symbolic step returns PB_ERR_UNSUPPORTED).
+ *                 Batched plans follow it too.  0 = off. */
 typedef struct {
     int32_t tile_tuples;
     int32_t expand_chunk;
@@ -124,7 +137,7 @@ typedef struct {
     int32_t run_align;
     int32_t row_count;
     int32_t convert;
-    int32_t reserved;
+    int32_t deterministic;
 } pb_tune;
 
 /* Plan facts (host copy, filled by the symbolic step). */
@@ -141,6 +154,8 @@ typedef struct {
     int64_t slots;            /* tuple slots (flop plus run padding) */
     int32_t run_align;        /* run alignment in slots */
     int32_t row_count;        /* 1 device atomics, 2 row buckets (see pb_tune) */
+    int32_t deterministic;    /* 1 if the plan sums in the fixed order (see pb_tune) */
+    int32_t reserved;
 } pb_plan_info;
 
 typedef struct pb_plan pb_plan; /* opaque, host-side */

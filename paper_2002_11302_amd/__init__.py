@@ -133,6 +133,7 @@ def _tune(tune):
     t.run_align = int(tune.get("run_align", 0))
     t.row_count = int(tune.get("row_count", 0))
     t.convert = int(tune.get("convert", 0))
+    t.deterministic = int(tune.get("deterministic", 0))
     return ctypes.byref(t)
 
 

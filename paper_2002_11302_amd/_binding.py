@@ -45,7 +45,7 @@ class PbCsrOut(ctypes.Structure):
 class PbTune(ctypes.Structure):
     _fields_ = [("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("round_tuples", ctypes.c_int64),
                 ("run_align", ctypes.c_int32), ("row_count", ctypes.c_int32),
-                ("convert", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("convert", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class PbPlanInfo(ctypes.Structure):
@@ -55,6 +55,7 @@ class PbPlanInfo(ctypes.Structure):
         ("tile_tuples", ctypes.c_int32), ("expand_chunk", ctypes.c_int32), ("col_bits", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("count", ctypes.c_int64), ("slots", ctypes.c_int64),
         ("run_align", ctypes.c_int32), ("row_count", ctypes.c_int32),
+        ("deterministic", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

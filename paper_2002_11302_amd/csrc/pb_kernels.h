@@ -252,6 +252,10 @@ struct RowBucketArgs {
     const RowTab *rowtab;  // per row: first slot and row inside its bin
     uint64_t *entrec;             // bucket order: the record's run destination (ent_pack)
     uint64_t *ent;                // entry order: the entry's run destination
+    // fixed order only (null otherwise)
+    uint32_t *recent;             // bucket order: the record's entry of A
+    uint32_t *lste, *lsts, *lstp; // per bucket, grouped by row: entry, run slots, record
+    int64_t det_tmax;             // the tile: wider rows are not ordered
 };
 
 template <int BLOCK>
@@ -317,6 +321,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(RowBucketArgs a) {
         a.rec[pos] = (uint32_t)(r & (kRowBucketRows - 1)) | field << kRowBucketBits;
         if (field == kRunField) a.roff[pos] = (uint32_t)k;
         a.posof[e] = pos;
+        if (a.recent) a.recent[pos] = (uint32_t)e;
     };
     if (nc <= kBucketCols) {
         for (int64_t i = threadIdx.x; i <= nc; i += BLOCK) {
@@ -391,6 +396,107 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t
             const uint64_t old = atomicAdd(&s_cnt[rc[u] & (kRowBucketRows - 1)], (unsigned long long)slots);
             a.roff[p + u * BLOCK] = (uint32_t)old;
         }
+    }
+    __syncthreads();
+    const int64_t r0 = b << kRowBucketBits;
+    for (int i = threadIdx.x; i < kRowBucketRows && r0 + i < m; i += BLOCK) a.rowflop[r0 + i] = s_cnt[i];
+}
+
+// Pass 3, fixed order: the same per-row totals, but a run's offset in its
+// row is the sum of the slots of the row's runs from earlier entries of A
+// (A is column-major, so earlier entries of one row are earlier columns),
+// whatever order the scatter left the records in.  The bucket's records
+// with at least one slot are first grouped by row (a counting sort into
+// lste/lsts/lstp over the bucket's own record range); each then adds up the
+// slots of its row's records with a smaller entry index.  A row is at most
+// det_tmax slots, so it has at most that many such records; a wider row
+// is skipped (the plan is then refused).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_count_det(RowBucketArgs a, int64_t m) {
+    constexpr int RPT = kRowBucketRows / BLOCK;
+    static_assert(kRowBucketRows % BLOCK == 0, "whole rows per thread");
+    __shared__ unsigned long long s_cnt[kRowBucketRows];
+    __shared__ uint32_t s_n[kRowBucketRows];      // records per row (fill cursors in between)
+    __shared__ uint32_t s_start[kRowBucketRows];  // the row's first record in the grouped lists
+    __shared__ uint64_t s_red[BLOCK / kWave];
+    __shared__ uint64_t s_scan[BLOCK / kWave + 1];
+    for (int i = threadIdx.x; i < kRowBucketRows; i += BLOCK) {
+        s_cnt[i] = 0;
+        s_n[i] = 0;
+    }
+    const int64_t b = blockIdx.x;
+    if (b == 0) {
+        uint64_t f = 0;
+        for (int g = threadIdx.x; g < a.ngrp; g += BLOCK) f += a.gflop[g];
+        f = block_sum<BLOCK>(f, s_red);
+        if (threadIdx.x == 0) a.info->flop = f;
+    }
+    __syncthreads();
+    const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
+    auto slots_of = [&](uint32_t p, uint32_t rc) -> uint64_t {
+        uint64_t sl = rc >> kRowBucketBits;
+        if (sl == kRunField) {
+            const uint32_t k = a.roff[p];
+            sl = (uint64_t)run_slots(a.brp[k + 1] - a.brp[k], a.align);
+        }
+        return sl;
+    };
+    for (int64_t pp = (int64_t)p0 + threadIdx.x; pp < p1; pp += BLOCK) {
+        const uint32_t p = (uint32_t)pp;
+        const uint32_t rc = a.rec[p];
+        const uint32_t row = rc & (kRowBucketRows - 1);
+        const uint64_t sl = slots_of(p, rc);
+        if (sl) {
+            atomicAdd(&s_cnt[row], (unsigned long long)sl);
+            atomicAdd(&s_n[row], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t listed;
+    {
+        uint32_t c[RPT];
+        uint64_t t = 0;
+#pragma unroll
+        for (int x = 0; x < RPT; ++x) {
+            c[x] = s_n[threadIdx.x * RPT + x];
+            t += c[x];
+        }
+        uint64_t total;
+        uint64_t ex = block_excl_scan<BLOCK, SumOp>(t, s_scan, total);
+        listed = (uint32_t)total;
+#pragma unroll
+        for (int x = 0; x < RPT; ++x) {
+            s_start[threadIdx.x * RPT + x] = (uint32_t)ex;
+            s_n[threadIdx.x * RPT + x] = 0;
+            ex += c[x];
+        }
+    }
+    __syncthreads();
+    for (int64_t pp = (int64_t)p0 + threadIdx.x; pp < p1; pp += BLOCK) {
+        const uint32_t p = (uint32_t)pp;
+        const uint32_t rc = a.rec[p];
+        const uint32_t row = rc & (kRowBucketRows - 1);
+        const uint64_t sl = slots_of(p, rc);
+        if (sl) {
+            const uint32_t q = p0 + s_start[row] + atomicAdd(&s_n[row], 1u);
+            a.lste[q] = a.recent[p];
+            a.lsts[q] = (uint32_t)sl;
+            a.lstp[q] = p;
+        } else {
+            a.roff[p] = 0;  // a run of no tuples
+        }
+    }
+    __syncthreads();
+    for (int64_t qq = (int64_t)p0 + threadIdx.x; qq < (int64_t)p0 + listed; qq += BLOCK) {
+        const uint32_t q = (uint32_t)qq;
+        const uint32_t p = a.lstp[q];
+        const uint32_t row = a.rec[p] & (kRowBucketRows - 1);
+        if (s_cnt[row] > (unsigned long long)a.det_tmax) continue;  // a wide row: refused after the step
+        const uint32_t e = a.lste[q];
+        const uint32_t l0 = p0 + s_start[row], l1 = l0 + s_n[row];
+        uint64_t off = 0;
+        for (uint32_t x = l0; x < l1; ++x) off += a.lste[x] < e ? a.lsts[x] : 0u;
+        a.roff[p] = (uint32_t)off;
     }
     __syncthreads();
     const int64_t r0 = b << kRowBucketBits;
@@ -1140,6 +1246,9 @@ struct SortArgs {
     const uint32_t *bignnz;      // rounds: entries of C of each wide row, indexed by row - row_base
     const int64_t *rowptr_base;  // entries of C before the launch's first row (null: none)
     int64_t rows_end;            // single product: one past the launch's last row
+    // fixed summation order (k_sort_compress<..., true>): equal keys ordered by
+    // slot, each entry of C summed one tuple at a time from its first tuple
+    int det;
 };
 
 template <class VT>
@@ -1235,8 +1344,11 @@ __device__ __forceinline__ void load_bin(const uint32_t *keys, const void *vals,
 
 constexpr uint32_t kBucketLimit = 40;
 
-template <int BLOCK, int TMAX, class VT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2048 ? 5 : 1))) void k_sort_compress(SortArgs a) {
+// DET: the fixed summation order (stable ranks, no hash pre-sum, every run
+// summed by its head); a separate instance, so the default one keeps its
+// registers.
+template <int BLOCK, int TMAX, class VT, bool DET = false>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2048 && !DET ? 5 : 1))) void k_sort_compress(SortArgs a) {
     constexpr int NW = BLOCK / kWave;
     constexpr int IPT = TMAX / BLOCK;
     constexpr int NB = TMAX >= 4096 ? TMAX : TMAX / 2;  // buckets of the one-pass path
@@ -1310,7 +1422,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2
     // distinct keys, each with its sum, go on to the sort.
     {
         const int64_t D = bend - base;
-        if (D > 0 && 2 * D <= N && D <= TMAX / 2) {
+        if (!DET && D > 0 && 2 * D <= N && D <= TMAX / 2) {
             constexpr int TSD = TMAX;  // table slots, load factor <= 1/2
             constexpr int LOG_TSD = (TSD >= 4096) ? 12 : (TSD >= 2048) ? 11 : (TSD >= 1024) ? 10 : 9;
             static_assert((1 << LOG_TSD) == TSD, "table size");
@@ -1469,10 +1581,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2
                 const uint32_t be = hist[bk];
                 const uint32_t bs = bk ? hist[bk - 1] : 0u;
                 uint32_t rank = bs;
-                for (uint32_t x = bs; x < be; x += 2) {
-                    const uint32_t k0 = keyB[x], k1 = keyB[x + 1];  // x + 1 stays inside the LDS arrays
-                    rank += (k0 < key) || (k0 == key && x < (uint32_t)q);
-                    if (x + 1 < be) rank += (k1 < key) || (k1 == key && x + 1 < (uint32_t)q);
+                if constexpr (!DET) {
+                    // equal keys in bucket order (any order sums the same up to rounding)
+                    for (uint32_t x = bs; x < be; x += 2) {
+                        const uint32_t k0 = keyB[x], k1 = keyB[x + 1];  // x + 1 stays inside the LDS arrays
+                        rank += (k0 < key) || (k0 == key && x < (uint32_t)q);
+                        if (x + 1 < be) rank += (k1 < key) || (k1 == key && x + 1 < (uint32_t)q);
+                    }
+                } else {
+                    // equal keys in slot order: a stable sort
+                    const uint32_t sq = slotB[q];
+                    for (uint32_t x = bs; x < be; ++x) {
+                        const uint32_t kx = keyB[x];
+                        rank += (kx < key) || (kx == key && slotB[x] < sq);
+                    }
                 }
                 keyA[rank] = key;
                 slotA[rank] = slotB[q];
@@ -1601,8 +1723,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2
         heads += s_wsum[ww];
     }
     VT *cv = (VT *)cvals;
-    if ((uint32_t)Nr - heads <= (uint32_t)Nr / 16) {
-        // few repeated keys: each head sums its (short) run itself.  The
+    if (DET || (uint32_t)Nr - heads <= (uint32_t)Nr / 16) {
+        // few repeated keys (or the fixed order): each head sums its run
+        // itself, left to right.  The
         // LDS reads of all of a thread's heads are issued together.
         uint32_t hk[IPT], hs[IPT], hn[IPT];
         VT hv[IPT];

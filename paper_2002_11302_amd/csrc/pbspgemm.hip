@@ -179,14 +179,19 @@ int col_bits(int64_t n) {
 }
 
 pb_status resolve_tune(const pb_tune *t, int default_tile, int *T, int *chunk, int64_t *round_tuples, int *align,
-                       int *rowcount, int *convert) {
+                       int *rowcount, int *convert, int *det) {
     *T = default_tile;
     *chunk = kDefaultChunk;
     *round_tuples = 0;
     *align = 0;
     *rowcount = 0;
     *convert = 1;
+    *det = 0;
     if (!t) return PB_OK;
+    if (t->deterministic != 0 && t->deterministic != 1) return fail(PB_ERR_ARG, "deterministic must be 0 or 1");
+    *det = t->deterministic;
+    if (*det && t->convert == 2) return fail(PB_ERR_ARG, "deterministic mode takes convert 0 or 1");
+    if (*det && t->row_count == 1) return fail(PB_ERR_ARG, "deterministic mode needs row buckets (row_count 0 or 2)");
     if (t->convert < 0 || t->convert > 2) return fail(PB_ERR_ARG, "convert must be 0 (auto), 1 or 2");
     *convert = t->convert ? t->convert : 1;
     if (t->row_count < 0 || t->row_count > 2) return fail(PB_ERR_ARG, "row_count must be 0 (auto), 1 or 2");
@@ -223,6 +228,7 @@ struct pb_plan {
     int align = 1;  // run alignment in tuple slots
     int rowcount = 1;  // per-row flop: 1 device atomics, 2 row buckets
     int convert = 1;   // ConvertCSR: 1 count pass + row scan, 2 fused into the sort
+    int det = 0;       // fixed summation order (runs in column order of A, stable sort, left-to-right sums)
     // symbolic workspace tables
     SymInfo *info = nullptr;
     int64_t *F = nullptr;
@@ -287,6 +293,7 @@ struct SymLayout {
     uint32_t *rec, *roff;
     uint32_t *posof;
     uint64_t *entrec;
+    uint32_t *recent, *lste, *lsts, *lstp;  // fixed order only
     int nbkt, ngrp;
     int64_t epw, cpw;
     // batch only
@@ -326,7 +333,8 @@ int pick_rowcount(int requested, int64_t m, int64_t k, int64_t nnza) {
     return ok ? 2 : 1;
 }
 
-SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnzb, int32_t count, int rowcount) {
+SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnzb, int32_t count, int rowcount,
+                     int det) {
     Carver cv(base);
     SymLayout L{};
     BucketShape bs{};
@@ -358,6 +366,12 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
         L.roff = cv.take<uint32_t>(nnza);
         L.posof = cv.take<uint32_t>(nnza);
         L.entrec = cv.take<uint64_t>(nnza);
+        if (det) {
+            L.recent = cv.take<uint32_t>(nnza);
+            L.lste = cv.take<uint32_t>(nnza);
+            L.lsts = cv.take<uint32_t>(nnza);
+            L.lstp = cv.take<uint32_t>(nnza);
+        }
     }
     if (count > 1) {
         L.pdesc = cv.take<ProbDesc>(count);
@@ -477,6 +491,11 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
             ra.rowtab = L.rowtab;
             ra.entrec = L.entrec;
             ra.ent = L.ent;
+            ra.recent = L.recent;
+            ra.lste = L.lste;
+            ra.lsts = L.lsts;
+            ra.lstp = L.lstp;
+            ra.det_tmax = p->T;
             const int64_t nh = (int64_t)L.nbkt * L.ngrp;
             const size_t lds = (size_t)L.nbkt * sizeof(uint32_t);
             const dim3 grid((unsigned)L.ngrp), block(kBucketBlock);
@@ -486,7 +505,8 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
                                       &L.info->err, st, "bucket scan"));
             hipLaunchKernelGGL(k_bucket_scatter<kBucketBlock>, grid, block, lds, st, ra);
             PB_LAUNCHED("bucket scatter");
-            hipLaunchKernelGGL(k_bucket_count<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
+            if (p->det) hipLaunchKernelGGL(k_bucket_count_det<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
+            else hipLaunchKernelGGL(k_bucket_count<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
             PB_LAUNCHED("bucket count");
             PB_TRY(run_row_bins(p, L, st));
             hipLaunchKernelGGL(k_bucket_dest<256>, dim3((unsigned)L.nbkt, 8), dim3(256), 0, st, ra, m);
@@ -532,11 +552,16 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
         }                                                                                                        \
     } while (0)
 
+// The fixed-order instances of the sort kernel, named for the launch macro.
+template <int BLOCK, int TMAX, class VT>
+constexpr auto k_sort_compress_det = k_sort_compress<BLOCK, TMAX, VT, true>;
+
 // Sort + compress launch for `nbins` bins of at most T tuples (T picks the
 // kernel shape; sa.fused the ConvertCSR mode).
 pb_status launch_sort(const pb_plan *p, int64_t T, const SortArgs &sa, int64_t nbins, hipStream_t st) {
     const bool f64 = p->prec == PB_F64;
     if (sa.fused) PB_SORT_LAUNCH(k_sort_compress_fused);
+    else if (sa.det) PB_SORT_LAUNCH(k_sort_compress_det);
     else PB_SORT_LAUNCH(k_sort_compress);
     PB_LAUNCHED("sort+compress");
     return PB_OK;
@@ -882,6 +907,7 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
             sa.bignnz = L.rownnz;
             sa.rowptr_base = rowptr_base;
             sa.rows_end = rd.r1;
+            sa.det = p->det;
             PB_TRY(launch_sort(p, p->T, sa, nb, st));
         }
         if (rd.nbig) {
@@ -924,6 +950,11 @@ pb_status finish_symbolic(pb_plan *p, hipStream_t st) {
     if (p->h.maxrow >= ((uint64_t)1 << 32))
         return fail(PB_ERR_UNSUPPORTED, "a row of C expands to %llu tuples; at most 2^32 - 1 are supported",
                     (unsigned long long)p->h.maxrow);
+    if (p->h.noversize && p->det)
+        return fail(PB_ERR_UNSUPPORTED,
+                    "%llu rows expand to more than %d tuples (largest %lld); the fixed summation order needs every "
+                    "row within the tile",
+                    (unsigned long long)p->h.noversize, p->T, (long long)p->h.maxrow);
     if (p->h.noversize && p->count > 1)
         return fail(PB_ERR_UNSUPPORTED,
                     "%llu rows expand to more than %d tuples (largest %lld); batched products need every row within "
@@ -1015,6 +1046,7 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
         sa.fused = fused ? 1 : 0;
         sa.ticket = L.sticket;
         sa.status = L.sstatus;
+        sa.det = p->det;
         ProfScope ps(st, 2);
         PB_TRY(launch_sort(p, p->T, sa, nbins, st));
     }
@@ -1179,14 +1211,17 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
         return fail(PB_ERR_SHAPE, "A.ncols (%lld) != B.nrows (%lld)", (long long)A->ncols, (long long)B->nrows);
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk, align, rowreq, convert;
+    int T, chunk, align, rowreq, convert, det;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, kDefaultTile, &T, &chunk, &round_tuples, &align, &rowreq, &convert));
+    PB_TRY(resolve_tune(tune, kDefaultTile, &T, &chunk, &round_tuples, &align, &rowreq, &convert, &det));
     const int64_t m = A->nrows, k = A->ncols, n = B->ncols;
     const int rowcount = pick_rowcount(rowreq, m, k, A->nnz);
     if (rowcount < 0)
         return fail(PB_ERR_ARG, "row_count 2 needs 0 < nnz(A) < 2^32 and at most %d rows", kMaxRowBuckets * kRowBucketRows);
-    const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1, rowcount).total;
+    if (det && rowcount != 2)
+        return fail(PB_ERR_ARG, "deterministic mode needs row buckets: 0 < nnz(A) < 2^32 and at most %d rows",
+                    kMaxRowBuckets * kRowBucketRows);
+    const size_t need = sym_layout(nullptr, m, k, A->nnz, B->nnz, 1, rowcount, det).total;
     if (!sym_ws) {
         *sym_ws_bytes = need;
         return PB_OK;
@@ -1203,7 +1238,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
         PB_TRY(validate_csx(A, "A", true, st));
         PB_TRY(validate_csx(B, "B", false, st));
     }
-    SymLayout L = sym_layout(sym_ws, m, k, A->nnz, B->nnz, 1, rowcount);
+    SymLayout L = sym_layout(sym_ws, m, k, A->nnz, B->nnz, 1, rowcount, det);
     pb_plan *p = new pb_plan();
     p->rowcount = rowcount;
     p->m = m;
@@ -1217,6 +1252,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->cb = cb;
     p->round_tuples = round_tuples;
     p->convert = convert;
+    p->det = det;
     // FP64 runs padded to 4 slots (whole 32-byte sectors of values) when B's
     // rows are long enough on average for the padding to cost little next to
     // the partial-sector writes it avoids (measured: ER 2^20 d=16 step -3%;
@@ -1394,9 +1430,9 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     PB_TRY(check_batch(count, A, B));
     if (prec != PB_F64 && prec != PB_F32C) return fail(PB_ERR_ARG, "unknown precision %d", (int)prec);
     if (!sym_ws_bytes) return fail(PB_ERR_ARG, "sym_ws_bytes is NULL");
-    int T, chunk, align, rowreq, convert;
+    int T, chunk, align, rowreq, convert, det;
     int64_t round_tuples;
-    PB_TRY(resolve_tune(tune, kDefaultTileBatched, &T, &chunk, &round_tuples, &align, &rowreq, &convert));
+    PB_TRY(resolve_tune(tune, kDefaultTileBatched, &T, &chunk, &round_tuples, &align, &rowreq, &convert, &det));
     std::vector<ProbDesc> hd;
     int64_t m, k, n, nnza, nnzb;
     batch_shapes(count, A, B, hd, m, k, n, nnza, nnzb);
@@ -1407,7 +1443,10 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     const int rowcount = pick_rowcount(rowreq, m, k, nnza);
     if (rowcount < 0)
         return fail(PB_ERR_ARG, "row_count 2 needs 0 < nnz(A) < 2^32 and at most %d rows", kMaxRowBuckets * kRowBucketRows);
-    const size_t need = sym_layout(nullptr, m, k, nnza, nnzb, cnt, rowcount).total;
+    if (det && rowcount != 2)
+        return fail(PB_ERR_ARG, "deterministic mode needs row buckets: 0 < nnz(A) < 2^32 and at most %d rows",
+                    kMaxRowBuckets * kRowBucketRows);
+    const size_t need = sym_layout(nullptr, m, k, nnza, nnzb, cnt, rowcount, det).total;
     if (!sym_ws) {
         *sym_ws_bytes = need;
         return PB_OK;
@@ -1437,7 +1476,7 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     }
 
     hipStream_t st = (hipStream_t)hip_stream;
-    SymLayout L = sym_layout(sym_ws, m, k, nnza, nnzb, cnt, rowcount);
+    SymLayout L = sym_layout(sym_ws, m, k, nnza, nnzb, cnt, rowcount, det);
     pb_plan *p = new pb_plan();
     p->rowcount = rowcount;
     p->m = m;
@@ -1452,6 +1491,7 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     p->chunk = chunk;
     p->cb = cb;
     p->convert = convert;
+    p->det = det;
     p->info = L.info;
     p->F = L.F;
     p->R = L.R;
@@ -1599,6 +1639,7 @@ pb_status spgemm_plan_info(const pb_plan *p, pb_plan_info *info) {
     info->slots = (int64_t)p->h.slots;
     info->run_align = p->align;
     info->row_count = p->rowcount;
+    info->deterministic = p->det;
     info->nbins = (int64_t)p->h.nbins;
     info->max_bin_tuples = (int64_t)p->h.maxbin;
     info->max_row_flop = (int64_t)p->h.maxrow;

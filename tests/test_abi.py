@@ -113,7 +113,39 @@ def test_tune_struct_layout():
     assert B.PbTune.run_align.offset == 16
     assert B.PbTune.row_count.offset == 20
     assert B.PbTune.convert.offset == 24
+    assert B.PbTune.deterministic.offset == 28
     assert ctypes.sizeof(B.PbPlanInfo) % 8 == 0
+    assert B.PbPlanInfo.deterministic.offset == B.PbPlanInfo.row_count.offset + 4
+
+
+def test_deterministic_tune_checks(lib):
+    """The fixed summation order takes 0/1, needs row buckets and the
+    count-pass ConvertCSR; its symbolic workspace adds four 32-bit words
+    per entry of A (record entry, and the per-row grouped lists)."""
+    a, b = _fake(1000, 500, 3000), _fake(500, 700, 3000)
+    for field, value in (("deterministic", 2), ("deterministic", -1)):
+        t = B.PbTune()
+        setattr(t, field, value)
+        rc, _ = _symbolic(lib, a, b, tune=ctypes.byref(t))
+        assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
+    for field, value in (("convert", 2), ("row_count", 1)):
+        t = B.PbTune()
+        t.deterministic = 1
+        setattr(t, field, value)
+        rc, _ = _symbolic(lib, a, b, tune=ctypes.byref(t))
+        assert B.STATUS_NAMES[rc] == "PB_ERR_ARG", field
+    t = B.PbTune()
+    t.deterministic = 1
+    t.convert = 1
+    rc, det = _symbolic(lib, a, b, tune=ctypes.byref(t))
+    assert rc == 0
+    rc, plain = _symbolic(lib, a, b)
+    assert rc == 0 and det >= plain + 16 * 3000
+    # too many rows for row buckets: no fixed order
+    t = B.PbTune()
+    t.deterministic = 1
+    rc, _ = _symbolic(lib, _fake((1 << 25) + 1, 5, 3), _fake(5, 7, 3), tune=ctypes.byref(t))
+    assert B.STATUS_NAMES[rc] == "PB_ERR_ARG"
 
 
 def test_bad_row_count(lib):
