@@ -9,7 +9,7 @@
 // sub-range found by binary search.
 //
 // Wide rows ("hub" rows, whose tuples exceed the tile T): after the expand,
-// a wide row's tuples sit contiguously (the tuple array is in row order) in
+// a wide row's tuples sit contiguously (a wide row is a bin by itself) in
 // arbitrary column order.  They are partitioned by column window
 // (2^wbits consecutive columns) into a second buffer.  Each (row, window)
 // pair is a virtual row; virtual rows are cut into bins exactly like rows

@@ -7,8 +7,9 @@ namespace pb {
 
 // ---------------------------------------------------------------------------
 // Facts the symbolic step leaves on the device (read back once).
-// Per-row facts: where the row's tuples start in the row-ordered tuple
-// array, and the row's index inside its bin.
+// Per-row facts: R[r], the first slot of the row's share of the tuple
+// array (bins are consecutive slot ranges in row order; inside a bin the
+// runs of its rows may be interleaved), and the row's index inside its bin.
 struct RowTab {
     int64_t base;
     uint32_t rl;
@@ -219,11 +220,13 @@ __global__ __launch_bounds__(BLOCK) void k_rowflop(int64_t K, const int64_t *acp
 // the bucket-major histogram gives every (bucket, workgroup) pair its place,
 // and a second pass writes one record per entry there (and the record's
 // place, per entry).  One workgroup per bucket adds each record's run slots
-// to its row's LDS counter; the fetched value, the run's offset inside the
-// row, is stored beside the record.  A last pass over the entry ranges
-// copies each entry's offset: the records of one range sit in one short
-// segment per bucket, so these reads, like every write, are whole lines.
-// Same result as k_rowflop up to the order of the runs in a row.
+// to its row's LDS counter (the per-row tuple counts).  After the row scan
+// and the bin cut, one workgroup per bucket gives each record its run's
+// place inside its bin (an LDS cursor per part of a bin), and a last pass
+// over the entry ranges copies each entry's place: the records of one range
+// sit in one short segment per bucket, so these reads, like every write,
+// are whole lines.  The same bins as k_rowflop's; only the order of the
+// runs inside a bin differs.
 constexpr int kRowBucketBits = 12;
 constexpr int kRowBucketRows = 1 << kRowBucketBits;
 constexpr int kMaxRowBuckets = 8192;      // LDS histogram of the distribution
@@ -364,8 +367,9 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(RowBucketArgs a) {
     }
 }
 
-// Pass 3: one workgroup per bucket; block 0 also adds up the multiplication
-// count.
+// Pass 3: one workgroup per bucket sums its records' slots per row (the
+// rows' tuple counts for the row scan and the bin cut); block 0 also adds up
+// the multiplication count.  roff keeps the column of saturated records.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t m) {
     __shared__ unsigned long long s_cnt[kRowBucketRows];
@@ -393,8 +397,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count(RowBucketArgs a, int64_t
                 const uint32_t k = a.roff[p + u * BLOCK];
                 slots = (uint64_t)run_slots(a.brp[k + 1] - a.brp[k], a.align);
             }
-            const uint64_t old = atomicAdd(&s_cnt[rc[u] & (kRowBucketRows - 1)], (unsigned long long)slots);
-            a.roff[p + u * BLOCK] = (uint32_t)old;
+            atomicAdd(&s_cnt[rc[u] & (kRowBucketRows - 1)], (unsigned long long)slots);
         }
     }
     __syncthreads();
@@ -503,12 +506,62 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_count_det(RowBucketArgs a, int
     for (int i = threadIdx.x; i < kRowBucketRows && r0 + i < m; i += BLOCK) a.rowflop[r0 + i] = s_cnt[i];
 }
 
-// Pass 4 (after the row scan and the bin cut): the workgroups of a bucket
-// (gridDim.y slices of its records) hold its rows' first slots and
-// rows-in-bin in LDS and turn every record's run offset into the run's
-// destination word.
+// Pass 4 (after the row scan and the bin cut): one workgroup per bucket
+// places every record's run inside its bin.  The runs of a bin are not
+// grouped by row (the sort orders the bin anyway): the part of a bin inside
+// the bucket (its rows there, a "segment") is filled by one LDS cursor in
+// record order, which follows the entry order of A and so the column order
+// the expand runs in.  Runs that are neighbours in memory are then written
+// close together in time, and a bin has one partly written line of keys
+// and one of values at a time instead of one per row, so far fewer partial
+// lines leave the caches (ER n=2^20, d=16: expand 2.13 -> 2.01 ms).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_bucket_dest(RowBucketArgs a, int64_t m) {
+    __shared__ uint64_t s_base[kRowBucketRows];          // per row: its slot range's first slot
+    __shared__ unsigned long long s_cur[kRowBucketRows];  // per segment (by its first row): fill cursor
+    __shared__ uint32_t s_rl[kRowBucketRows];
+    __shared__ uint16_t s_first[kRowBucketRows];          // per row: its segment's first row in the bucket
+    const int64_t b = blockIdx.x;
+    const int64_t r0 = b << kRowBucketBits;
+    for (int i = threadIdx.x; i < kRowBucketRows; i += BLOCK) {
+        s_cur[i] = 0;
+        if (r0 + i < m) {
+            const RowTab rt = a.rowtab[r0 + i];
+            s_base[i] = (uint64_t)rt.base;
+            s_rl[i] = rt.rl;
+            s_first[i] = (uint16_t)((uint32_t)i > rt.rl ? (uint32_t)i - rt.rl : 0u);
+        }
+    }
+    __syncthreads();
+    const uint32_t p0 = a.hist[b * a.ngrp], p1 = a.hist[(b + 1) * a.ngrp];
+    constexpr int U = 4;
+    for (int64_t p = (int64_t)p0 + threadIdx.x; p < p1; p += (int64_t)BLOCK * U) {
+        uint32_t rc[U], kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = p + u * BLOCK < p1 ? p + u * BLOCK : p1 - 1;  // unconditional loads overlap
+            rc[u] = a.rec[q];
+            kk[u] = a.roff[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p + u * BLOCK >= p1) break;
+            const uint32_t row = rc[u] & (kRowBucketRows - 1);
+            uint64_t slots = rc[u] >> kRowBucketBits;
+            if (slots == kRunField) slots = (uint64_t)run_slots(a.brp[kk[u] + 1] - a.brp[kk[u]], a.align);
+            const uint32_t f = s_first[row];
+            const uint64_t off = atomicAdd(&s_cur[f], (unsigned long long)slots);
+            a.entrec[p + u * BLOCK] = ent_pack(s_base[f] + off, s_rl[row]);
+        }
+    }
+}
+
+// Pass 4 of the fixed summation order: runs stay grouped by row, each at
+// the offset k_bucket_count_det gave it (the workgroups of a bucket take
+// gridDim.y slices of its records; the bucket's rows' first slots and
+// rows-in-bin are held in LDS).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bucket_dest_rows(RowBucketArgs a, int64_t m) {
     __shared__ uint64_t s_base[kRowBucketRows];
     __shared__ uint32_t s_rl[kRowBucketRows];
     const int64_t b = blockIdx.x;
@@ -733,9 +786,9 @@ __global__ void k_chunk_start(int64_t nchunks, int64_t C, int64_t K, const int64
 // the product of the i-th entry of A(:,k) and the j-th entry of B(k,:),
 // (i, j) = divmod(t - F[k], run slots of B(k,:)); slots with j past
 // nnz(B(k,:)) are run padding and get the sentinel key.  The tuples of one
-// A entry e = (r, k) form a run that goes to row r's range of the
-// row-ordered tuple array, at offset runpos[e] (fixed by the symbolic step),
-// so bins are contiguous row ranges and no append needs an atomic.
+// A entry e = (r, k) form a run that goes to the slots of r's bin, at the
+// place ent[e] the symbolic step fixed, so every bin is one contiguous slot
+// range and no append needs an atomic.
 // Consecutive lanes take consecutive tuples, so each run is written by
 // consecutive lanes to consecutive addresses.
 struct ExpandArgs {
@@ -990,9 +1043,9 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
 }
 
 // ---------------------------------------------------------------------------
-// ConvertCSR, part 1: entries per row of C.  The tuple array is in row
-// order (each row's tuples are contiguous), so nnz(C(r,:)) is the number of
-// distinct keys among row r's tuples.  One workgroup per bin inserts the
+// ConvertCSR, part 1: entries per row of C.  A bin's tuples are contiguous
+// and carry their row inside the bin in the key, so nnz(C(r,:)) is the
+// number of distinct keys with r's row bits.  One workgroup per bin inserts the
 // bin's keys into an LDS hash set (open addressing, linear probing); once
 // every key is in, each occupied slot adds one to its key's row.  Only keys
 // are read.
@@ -1189,7 +1242,7 @@ struct SegRowPtrDst : NoSide {
 
 // ---------------------------------------------------------------------------
 // Sort + compress, one workgroup per bin.  The bin's N <= TMAX tuples (a
-// contiguous row range of the tuple array) are loaded once, every load
+// contiguous slot range of the tuple array) are loaded once, every load
 // issued before the first use; keys are ordered in LDS together with 16-bit
 // slot numbers while the values wait in registers; the values are then
 // parked in LDS by slot.  Equal keys are summed in sorted order by the first

@@ -509,7 +509,8 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
             else hipLaunchKernelGGL(k_bucket_count<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
             PB_LAUNCHED("bucket count");
             PB_TRY(run_row_bins(p, L, st));
-            hipLaunchKernelGGL(k_bucket_dest<256>, dim3((unsigned)L.nbkt, 8), dim3(256), 0, st, ra, m);
+            if (p->det) hipLaunchKernelGGL(k_bucket_dest_rows<256>, dim3((unsigned)L.nbkt, 8), dim3(256), 0, st, ra, m);
+            else hipLaunchKernelGGL(k_bucket_dest<1024>, dim3((unsigned)L.nbkt), dim3(1024), 0, st, ra, m);
             PB_LAUNCHED("bucket destinations");
             hipLaunchKernelGGL(k_bucket_offsets<kBucketBlock>, grid, block, 0, st, ra);
             PB_LAUNCHED("bucket offsets");
