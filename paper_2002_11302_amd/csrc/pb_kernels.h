@@ -931,13 +931,112 @@ __device__ __forceinline__ void expand_lanes(const int64_t *__restrict__ F, cons
     if (bad) atomic_or_agent(err, (uint32_t)kErrBinOverflow);
 }
 
-// One wave per chunk of W tuples.  The wave walks the columns its chunk
-// touches; the column's facts (F[k], where A(:,k) and B(k,:) start, nnz of
-// B(k,:)) are wave-uniform, and each lane takes one tuple of the current
-// 64-tuple step: (i, j) = divmod(t - F[k], nnz(B(k,:))).
-// The body takes every array as a restrict pointer: the arrays it reads are
-// never written by it, so loads of wave-uniform column facts can go through
-// the scalar cache and loads need not wait for earlier stores.
+// Chunks that span at most kShortCols + 1 columns, software-pipelined: the
+// wave takes its chunk in groups of U 64-tuple steps and issues the loads of
+// the next group before the stores of the current one.  Vector loads and
+// stores share one in-order completion counter, so a wave that waited for a
+// load issued after its stores would also wait for those stores; issued the
+// other way round, the stores of one group stay in flight while the wave
+// waits for the next group's operands.  Each lane finds its tuple's column
+// among the chunk's columns (their starts relative to the chunk sit in
+// scalar registers), then (A entry, B entry) = divmod(offset in the column,
+// run slots of B's row); a slot past nnz(B(k,:)) is run padding.
+template <class VT, int U>
+struct ExpandGroup {
+    uint64_t en[U];
+    double av[U], bv[U];
+    uint32_t col[U], j[U], nb[U];
+    bool on[U];
+};
+
+template <int W, class VT>
+__device__ __forceinline__ void expand_flat(const int64_t *__restrict__ F, const int64_t *__restrict__ acp,
+                                            const int64_t *__restrict__ astart, const int64_t *__restrict__ brp,
+                                            const uint64_t *__restrict__ ent, const double *__restrict__ avv,
+                                            const int32_t *__restrict__ bci, const double *__restrict__ bvals,
+                                            const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
+                                            int64_t flop, int64_t slot0, int align, int64_t kb, int nc, int64_t t0,
+                                            int64_t t1) {
+    constexpr int U = 4;
+    constexpr int GS = U * kWave;  // tuples per group
+    const int lane = (int)lane_id();
+    // one column per lane: where its slots start, B's row, A's column
+    int64_t fF = 0, fA = 0, fB = 0;
+    int32_t fN = 0;
+    int32_t rel = W;  // column start relative to t0, clamped to [-1, W]
+    if (lane < nc) {
+        const int64_t k = kb + lane;
+        fF = F[k];
+        fB = brp[k];
+        fN = (int32_t)(brp[k + 1] - fB);
+        fA = astart ? astart[k] : acp[k];
+        const int64_t d = fF - t0;
+        rel = d < -1 ? -1 : (d > W ? W : (int32_t)d);
+    }
+    int32_t rs[kShortCols + 1];
+#pragma unroll
+    for (int l = 0; l <= kShortCols; ++l) rs[l] = __builtin_amdgcn_readlane(rel, l);
+    const int last = (int)(t1 - 1 - t0);
+    bool bad = false;
+    auto issue = [&](int g, ExpandGroup<VT, U> &G) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = g * GS + u * kWave + lane;
+            G.on[u] = o <= last;
+            const int oc = o <= last ? o : last;  // lanes past the end load the last tuple's operands
+            int c = 0;
+#pragma unroll
+            for (int l = 1; l <= kShortCols; ++l) c += rs[l] <= oc ? 1 : 0;
+            const int64_t Fc = __shfl(fF, c, kWave);
+            const int64_t Bc = __shfl(fB, c, kWave);
+            const int64_t Ac = __shfl(fA, c, kWave);
+            const uint32_t Nc = (uint32_t)__shfl(fN, c, kWave);
+            int64_t i = 0, j = 0;
+            if (Nc > 0) divmod_u(t0 + oc - Fc, run_slots(Nc, align), i, j);
+            const uint32_t jb = (uint32_t)j < Nc ? (uint32_t)j : Nc - 1u;  // padding reads the run's last B entry
+            const int64_t e = Nc > 0 ? Ac + i : 0;
+            const int64_t bi = Nc > 0 ? Bc + jb : 0;
+            G.en[u] = ent[e];
+            G.av[u] = avv[e];
+            G.col[u] = (uint32_t)bci[bi];
+            G.bv[u] = bvals[bi];
+            G.j[u] = (uint32_t)j;
+            G.nb[u] = Nc;
+        }
+    };
+    auto finish = [&](const ExpandGroup<VT, U> &G) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!G.on[u]) continue;
+            if (G.nb[u] == 0) {  // no column of the chunk holds this slot: a broken plan
+                bad = true;
+                continue;
+            }
+            const int64_t slot = (int64_t)(G.en[u] & kEntSlotMask) - slot0 + G.j[u];
+            const bool real = G.j[u] < G.nb[u];
+            const uint32_t key = real ? (((uint32_t)(G.en[u] >> kEntSlotBits) << cb) | G.col[u]) : kSentinel;
+            if ((uint64_t)slot < (uint64_t)flop) tup.put(slot, key, real ? (VT)(G.av[u] * G.bv[u]) : (VT)0);
+            else bad = true;
+        }
+    };
+    const int ng = (int)((t1 - t0 + GS - 1) / GS);
+    ExpandGroup<VT, U> ga, gb;
+    issue(0, ga);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng) issue(g + 1, gb);
+        finish(ga);
+        if (g + 1 >= ng) break;
+        if (g + 2 < ng) issue(g + 2, ga);
+        finish(gb);
+    }
+    if (bad) atomic_or_agent(err, (uint32_t)kErrBinOverflow);
+}
+
+// One wave per chunk of W tuples: chunks over at most kShortCols + 1
+// columns take expand_flat, chunks over more (short columns: AMG, small d)
+// expand_lanes.  The body takes every array as a restrict pointer: the
+// arrays it reads are never written by it, so loads need not wait for
+// earlier stores.
 template <int W, class VT>
 __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const int32_t *__restrict__ kstart,
                                             const int64_t *__restrict__ acp, const int64_t *__restrict__ astart,
@@ -946,94 +1045,18 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
                                             const int32_t *__restrict__ bci, const double *__restrict__ bvals,
                                             const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
                                             int64_t flop, int64_t slot0, int align, int64_t nchunks, int64_t K) {
-    const uint32_t lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wave >= nchunks) return;
     const int64_t t0 = wave * (int64_t)W;
     const int64_t t1 = (t0 + W < flop) ? t0 + W : flop;
-    int64_t k = kstart[wave];
-    int64_t t = t0;
-    if (kstart[wave + 1] - k > kShortCols) {
+    const int64_t k = kstart[wave];
+    const int64_t nc = kstart[wave + 1] - k + 1;  // columns the chunk touches
+    if (nc > kShortCols + 1)
         expand_lanes<W, VT>(F, acp, astart, brp, ent, avv, bci, bvals, tup, err, cb, flop, slot0, align, K, k, t0,
                             t1);
-        return;
-    }
-    while (t < t1) {
-        const int64_t Fk1 = F[k + 1];
-        if (Fk1 <= t) {  // column with no tuples left in this chunk
-            ++k;
-            continue;
-        }
-        const int64_t Fk = F[k];
-        const int64_t bs = brp[k];
-        const int64_t nbt = brp[k + 1] - bs;       // B entries of the run
-        const int64_t nb = run_slots(nbt, align);  // its slots (flop space is in slots)
-        const uint32_t lastb = (uint32_t)nbt - 1u;
-        const int64_t as = astart ? astart[k] : acp[k];
-        const int64_t seg_end = Fk1 < t1 ? Fk1 : t1;
-        // column-local views: lanes index them with 32-bit offsets
-        const uint64_t *enk = ent + as;
-        const double *avk = avv + as;
-        const int32_t *bck = bci + bs;
-        const double *bvk = bvals + bs;
-        // this lane's first tuple of the segment as (A entry i, B entry j);
-        // later steps advance by (64 div nb, 64 mod nb) with a carry
-        int64_t i0, j0;
-        divmod_u(t - Fk + lane, nb, i0, j0);
-        uint32_t ii = (uint32_t)i0, jj = (uint32_t)j0;
-        const uint32_t nbu = (uint32_t)nb;
-        const uint32_t di = nbu > kWave ? 0u : (uint32_t)kWave / nbu;
-        const uint32_t dj = nbu > kWave ? (uint32_t)kWave : (uint32_t)kWave - di * nbu;
-        // the segment's last tuple: lanes past the end load its operands, so
-        // every load is unconditional and the loads of all steps can be in
-        // flight together (only the stores are guarded)
-        int64_t il, jl;
-        divmod_u(seg_end - 1 - Fk, nb, il, jl);
-        // four 64-tuple steps per iteration, every load issued before use
-        constexpr int U = 4;
-        for (int64_t tt = t; tt < seg_end; tt += U * kWave) {
-            uint32_t iu[U], ju[U];
-            bool on[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                on[u] = tt + u * kWave + lane < seg_end;
-                iu[u] = on[u] ? ii : (uint32_t)il;
-                ju[u] = on[u] ? jj : (uint32_t)jl;
-                ii += di;
-                jj += dj;
-                if (jj >= nbu) {
-                    jj -= nbu;
-                    ++ii;
-                }
-            }
-            uint64_t en[U];
-            uint32_t col[U];
-            double av[U], bvv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t jb = ju[u] < lastb ? ju[u] : lastb;  // padding slots read the run's last B entry
-                en[u] = enk[iu[u]];
-                av[u] = avk[iu[u]];
-                col[u] = (uint32_t)bck[jb];
-                bvv[u] = bvk[jb];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (on[u]) {
-                    const int64_t slot = (int64_t)(en[u] & kEntSlotMask) - slot0 + ju[u];
-                    const bool real = ju[u] <= lastb;
-                    const uint32_t key = real ? (((uint32_t)(en[u] >> kEntSlotBits) << cb) | col[u]) : kSentinel;
-                    if ((uint64_t)slot < (uint64_t)flop) {
-                        tup.put(slot, key, real ? (VT)(av[u] * bvv[u]) : (VT)0);
-                    } else {
-                        atomic_or_agent(err, (uint32_t)kErrBinOverflow);
-                    }
-                }
-            }
-        }
-        t = seg_end;
-        ++k;
-    }
+    else
+        expand_flat<W, VT>(F, acp, astart, brp, ent, avv, bci, bvals, tup, err, cb, flop, slot0, align, k, (int)nc,
+                           t0, t1);
 }
 
 template <int W, class VT>
