@@ -348,7 +348,35 @@ def bench_batched(pb, torch, steps, warmup):
                      "numeric_graph_frac_of_8TBps": round(mb / (graph_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)}
         log(f"batched {prec}: {res[prec]['whole_path_GFLOPS']} GFLOPS whole path, "
             f"{res[prec]['numeric_graph_GFLOPS']} GFLOPS numeric graph")
-        del outs, cache, sym, plan, ws
+        flops = list(plan.flops)
+        cache.clear()
+        del sym, plan, ws
+        torch.cuda.empty_cache()
+        # the same batch cut into flop size classes, each class its own
+        # block-diagonal batch with its own tuned tile and expand chunk
+        cb = autotune.ClassedBatch(pairs, prec, flops)
+        chosen = cb.choose(outs, log=log)
+        cb.run(outs, sync=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cb.symbolic()
+            cb.run(outs, sync=False)
+        torch.cuda.synchronize()
+        whole_c = (time.perf_counter() - t0) / steps
+        graph_c = _graph_ms(torch, lambda st: cb.run(outs, sync=False, stream=st), steps, warmup)
+        cb.close()
+        res[prec]["size_classes"] = {
+            "flop_bounds": list(autotune.SIZE_BOUNDS),
+            "classes": [{"count": ch["count"], "flop": ch["flop"],
+                         "tune": {"tile_tuples": ch["tile_tuples"], "expand_chunk": ch["expand_chunk"]},
+                         "autotune_cached": ch.get("cached")} for ch in chosen],
+            "whole_path_ms": round(whole_c * 1e3, 3), "whole_path_GFLOPS": round(2 * tot_flop / whole_c / 1e9, 2),
+            "numeric_graph_ms": round(graph_c, 3),
+            "numeric_graph_GFLOPS": round(2 * tot_flop / (graph_c * 1e-3) / 1e9, 2)}
+        log(f"batched {prec} by size class: {res[prec]['size_classes']['whole_path_GFLOPS']} GFLOPS whole path, "
+            f"{res[prec]['size_classes']['numeric_graph_GFLOPS']} GFLOPS numeric graph")
+        del outs, cb
         outs = None
         torch.cuda.empty_cache()
     # the plain FP64 path, one product at a time, everything preallocated
@@ -389,6 +417,10 @@ def bench_batched(pb, torch, steps, warmup):
         res[f"speedup_batched_{prec}_vs_sequential_f64"] = {
             "whole_path": round(seq / (res[prec]["whole_path_ms"] * 1e-3), 3),
             "numeric_graph": round(seq_graph / res[prec]["numeric_graph_ms"], 3)}
+        sc = res[prec]["size_classes"]
+        res[f"speedup_size_classes_{prec}_vs_sequential_f64"] = {
+            "whole_path": round(seq / (sc["whole_path_ms"] * 1e-3), 3),
+            "numeric_graph": round(seq_graph / sc["numeric_graph_ms"], 3)}
     res["speedup_batched_f32c_vs_batched_f64"] = {
         "whole_path": round(res["f64"]["whole_path_ms"] / res["f32c"]["whole_path_ms"], 3),
         "numeric_graph": round(res["f64"]["numeric_graph_ms"] / res["f32c"]["numeric_graph_ms"], 3)}

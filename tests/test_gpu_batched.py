@@ -241,3 +241,70 @@ def test_back_to_back_calls_into_different_outputs(pb):
             z = int(rp[-1].item())
             _check(dict(rowptr=rp.cpu().numpy(), colidx=ci[:z].cpu().numpy(), val=cv[:z].cpu().numpy()), ref, "f64")
     plan.close()
+
+
+def test_size_classes_match_oracle(pb, tmp_path):
+    """A batch cut into flop size classes (each class its own block-diagonal
+    batch with its own tile): every product equals the oracle, with fixed
+    per-class tunings, with tunings the tuner picks (cache in a temporary
+    file), and when the numeric steps of all classes are replayed from one
+    HIP graph."""
+    import torch
+
+    from paper_2002_11302_amd import autotune
+
+    probs = _uneven_batch(seed=13)
+    probs.append(er_problem(20000, 16, 301, 302, values="signed"))  # the largest class
+    pairs = [(pb.DeviceCsx.from_host(a), pb.DeviceCsx.from_host(b)) for a, b in probs]
+    flops = [int(np.dot(np.diff(a.ptr), np.diff(b.ptr))) if a.ncols else 0 for a, b in probs]
+    bounds = (1 << 14, 1 << 20)
+    groups = autotune.size_classes(flops, bounds)
+    assert len(groups) == 3 and sorted(sum(groups, [])) == list(range(len(probs)))
+    refs = [_ref(a, b) for a, b in probs]
+
+    def outputs(prec):
+        vdt = torch.float64 if prec == "f64" else torch.float32
+        return [(torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda"),
+                 torch.empty(max(f, 1), dtype=torch.int32, device="cuda"),
+                 torch.empty(max(f, 1), dtype=vdt, device="cuda")) for (a, _), f in zip(pairs, flops)]
+
+    def check(outs, nnz, prec, what):
+        for i, ((rp, ci, cv), z, ref) in enumerate(zip(outs, nnz, refs)):
+            got = dict(rowptr=rp.cpu().numpy(), colidx=ci[:z].cpu().numpy(), val=cv[:z].cpu().numpy())
+            _check(got, ref, prec)
+
+    for prec in ("f64", "f32c"):
+        _say(f"size classes, fixed tunings, {prec}")
+        tunes = [{"tile_tuples": 1024, "expand_chunk": 256}, {"tile_tuples": 2048, "expand_chunk": 1024},
+                 {"tile_tuples": 4096, "expand_chunk": 2048}]
+        cb = autotune.ClassedBatch(pairs, prec, flops, bounds=bounds, tunes=tunes)
+        outs = outputs(prec)
+        check(outs, cb.run(outs, sync=True), prec, "fixed")
+        cb.close()
+    _say("size classes, tuned, then one graph")
+    cb = autotune.ClassedBatch(pairs, "f64", flops, bounds=bounds)
+    outs = outputs("f64")
+    chosen = cb.choose(outs, reps=1, path=str(tmp_path / "tune.json"))
+    assert [c["count"] for c in chosen] == [len(g) for g in groups]
+    cb.symbolic()
+    nnz = cb.run(outs, sync=True)
+    check(outs, nnz, "f64", "tuned")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        cb.run(outs, sync=False, stream=side)
+        side.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            cb.run(outs, sync=False, stream=side)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for rp, ci, cv in outs:
+            rp.fill_(-1)
+            ci.fill_(-1)
+            cv.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check(outs, nnz, "f64", f"replay {rep}")
+    cb.close()
