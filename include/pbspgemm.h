@@ -163,6 +163,10 @@ typedef struct pb_plan pb_plan; /* opaque, host-side */
 /*
  * Symbolic step (Algorithm 3 plus the bin cut).
  *
+ * prec is a pb_precision value (PB_F64 or PB_F32C), passed as a plain
+ * 32-bit integer so that any value a caller passes is defined behaviour;
+ * others are PB_ERR_ARG.
+ *
  * Size query: with sym_ws == NULL, writes the symbolic workspace size to
  * *sym_ws_bytes and returns PB_OK without touching the device.
  *
@@ -174,7 +178,7 @@ typedef struct pb_plan pb_plan; /* opaque, host-side */
  * with spgemm_plan_destroy), *flop the multiplication count and
  * *workspace_bytes the device workspace spgemm_numeric needs.
  */
-pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, pb_precision prec,
+pb_status spgemm_symbolic(const pb_csx *A_csc, const pb_csx *B_csr, int32_t prec,
                           const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes,
                           void *hip_stream, pb_plan **plan, int64_t *flop,
                           size_t *workspace_bytes);
@@ -284,7 +288,7 @@ pb_status spgemm_numeric_round(pb_plan *plan, const pb_csx *A_csc, const pb_csx 
  * replay time, i.e. the descriptors of the latest call on the plan: capture
  * after the last eager call on the plan, or keep a plan per captured graph.
  */
-pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A_csc, const pb_csx *B_csr, pb_precision prec,
+pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A_csc, const pb_csx *B_csr, int32_t prec,
                                   const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes, void *hip_stream,
                                   pb_plan **plan, int64_t *flop, size_t *workspace_bytes);
 pb_status spgemm_batched(pb_plan *plan, int32_t count, const pb_csx *A_csc, const pb_csx *B_csr, void *workspace,

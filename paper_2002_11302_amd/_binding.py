@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpbspgemm.so")
+# PB_LIB names another build of the same library (the sanitizer test's host
+# build); there is no other implementation to fall back to.
+LIB_PATH = os.environ.get("PB_LIB") or os.path.join(_PKG, "libpbspgemm.so")
 
 PB_OK = 0
 STATUS_NAMES = {

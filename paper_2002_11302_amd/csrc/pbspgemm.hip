@@ -1202,7 +1202,7 @@ const char *spgemm_status_string(pb_status s) {
 
 const char *spgemm_last_error(void) { return g_last_error.c_str(); }
 
-pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, const pb_tune *tune, void *sym_ws,
+pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, int32_t prec, const pb_tune *tune, void *sym_ws,
                           size_t *sym_ws_bytes, void *hip_stream, pb_plan **plan, int64_t *flop,
                           size_t *workspace_bytes) {
     g_last_error.clear();
@@ -1247,7 +1247,7 @@ pb_status spgemm_symbolic(const pb_csx *A, const pb_csx *B, pb_precision prec, c
     p->n = n;
     p->nnzA = A->nnz;
     p->nnzB = B->nnz;
-    p->prec = prec;
+    p->prec = (pb_precision)prec;
     p->T = T;
     p->chunk = chunk;
     p->cb = cb;
@@ -1424,7 +1424,7 @@ pb_status spgemm_numeric_round(pb_plan *p, const pb_csx *A, const pb_csx *B, int
     return PB_OK;
 }
 
-pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *B, pb_precision prec,
+pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *B, int32_t prec,
                                   const pb_tune *tune, void *sym_ws, size_t *sym_ws_bytes, void *hip_stream,
                                   pb_plan **plan, int64_t *flop, size_t *workspace_bytes) {
     g_last_error.clear();
@@ -1487,7 +1487,7 @@ pb_status spgemm_batched_symbolic(int32_t count, const pb_csx *A, const pb_csx *
     p->nnzB = nnzb;
     p->count = cnt;
     p->user_count = count;
-    p->prec = prec;
+    p->prec = (pb_precision)prec;
     p->T = T;
     p->chunk = chunk;
     p->cb = cb;
