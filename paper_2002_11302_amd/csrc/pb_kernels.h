@@ -1032,9 +1032,92 @@ __device__ __forceinline__ void expand_flat(const int64_t *__restrict__ F, const
     if (bad) atomic_or_agent(err, (uint32_t)kErrBinOverflow);
 }
 
-// One wave per chunk of W tuples: chunks over at most kShortCols + 1
-// columns take expand_flat, chunks over more (short columns: AMG, small d)
-// expand_lanes.  The body takes every array as a restrict pointer: the
+// A chunk inside one column (long columns: hub rows of B times long columns
+// of A).  The column's facts are wave-uniform and each lane's (A entry,
+// B entry) pair advances by (64 div s, 64 mod s) per step with a carry (s:
+// the run's slots), so only the first step divides; the groups are
+// pipelined as in expand_flat.
+template <int W, class VT>
+__device__ __forceinline__ void expand_column(const int64_t *__restrict__ F, const int64_t *__restrict__ acp,
+                                              const int64_t *__restrict__ astart, const int64_t *__restrict__ brp,
+                                              const uint64_t *__restrict__ ent, const double *__restrict__ avv,
+                                              const int32_t *__restrict__ bci, const double *__restrict__ bvals,
+                                              const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
+                                              int64_t flop, int64_t slot0, int align, int64_t k, int64_t t0,
+                                              int64_t t1) {
+    constexpr int U = 4;
+    constexpr int GS = U * kWave;
+    const uint32_t lane = lane_id();
+    const int64_t Fk = F[k];
+    const int64_t bs = brp[k];
+    const uint32_t nbt = (uint32_t)(brp[k + 1] - bs);  // B entries of the run
+    if (nbt == 0) {  // no tuple can lie in this column: a broken plan
+        if (lane == 0) atomic_or_agent(err, (uint32_t)kErrBinOverflow);
+        return;
+    }
+    const uint32_t nbu = (uint32_t)run_slots(nbt, align);  // its slots
+    const int64_t as = astart ? astart[k] : acp[k];
+    const uint64_t *enk = ent + as;
+    const double *avk = avv + as;
+    const int32_t *bck = bci + bs;
+    const double *bvk = bvals + bs;
+    int64_t i0, j0, il, jl;
+    divmod_u(t0 - Fk + lane, nbu, i0, j0);
+    divmod_u(t1 - 1 - Fk, nbu, il, jl);  // the chunk's last tuple: lanes past the end load its operands
+    uint32_t ii = (uint32_t)i0, jj = (uint32_t)j0;
+    const uint32_t di = nbu > kWave ? 0u : (uint32_t)kWave / nbu;
+    const uint32_t dj = nbu > kWave ? (uint32_t)kWave : (uint32_t)kWave - di * nbu;
+    const int last = (int)(t1 - 1 - t0);
+    bool bad = false;
+    auto issue = [&](int g, ExpandGroup<VT, U> &G) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = g * GS + u * kWave + (int)lane;
+            G.on[u] = o <= last;
+            const uint32_t iu = G.on[u] ? ii : (uint32_t)il;
+            const uint32_t ju = G.on[u] ? jj : (uint32_t)jl;
+            ii += di;
+            jj += dj;
+            if (jj >= nbu) {
+                jj -= nbu;
+                ++ii;
+            }
+            const uint32_t jb = ju < nbt ? ju : nbt - 1u;  // padding reads the run's last B entry
+            G.en[u] = enk[iu];
+            G.av[u] = avk[iu];
+            G.col[u] = (uint32_t)bck[jb];
+            G.bv[u] = bvk[jb];
+            G.j[u] = ju;
+            G.nb[u] = nbt;
+        }
+    };
+    auto finish = [&](const ExpandGroup<VT, U> &G) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!G.on[u]) continue;
+            const int64_t slot = (int64_t)(G.en[u] & kEntSlotMask) - slot0 + G.j[u];
+            const bool real = G.j[u] < G.nb[u];
+            const uint32_t key = real ? (((uint32_t)(G.en[u] >> kEntSlotBits) << cb) | G.col[u]) : kSentinel;
+            if ((uint64_t)slot < (uint64_t)flop) tup.put(slot, key, real ? (VT)(G.av[u] * G.bv[u]) : (VT)0);
+            else bad = true;
+        }
+    };
+    const int ng = (int)((t1 - t0 + GS - 1) / GS);
+    ExpandGroup<VT, U> ga, gb;
+    issue(0, ga);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng) issue(g + 1, gb);
+        finish(ga);
+        if (g + 1 >= ng) break;
+        if (g + 2 < ng) issue(g + 2, ga);
+        finish(gb);
+    }
+    if (bad) atomic_or_agent(err, (uint32_t)kErrBinOverflow);
+}
+
+// One wave per chunk of W tuples: a chunk inside one column takes
+// expand_column, over at most kShortCols + 1 columns expand_flat, over more
+// (short columns: AMG, small d) expand_lanes.  The body takes every array as a restrict pointer: the
 // arrays it reads are never written by it, so loads need not wait for
 // earlier stores.
 template <int W, class VT>
@@ -1051,7 +1134,9 @@ __device__ __forceinline__ void expand_body(const int64_t *__restrict__ F, const
     const int64_t t1 = (t0 + W < flop) ? t0 + W : flop;
     const int64_t k = kstart[wave];
     const int64_t nc = kstart[wave + 1] - k + 1;  // columns the chunk touches
-    if (nc > kShortCols + 1)
+    if (nc == 1)
+        expand_column<W, VT>(F, acp, astart, brp, ent, avv, bci, bvals, tup, err, cb, flop, slot0, align, k, t0, t1);
+    else if (nc > kShortCols + 1)
         expand_lanes<W, VT>(F, acp, astart, brp, ent, avv, bci, bvals, tup, err, cb, flop, slot0, align, K, k, t0,
                             t1);
     else
