@@ -87,7 +87,11 @@ typedef struct {
     int64_t capacity;
 } pb_csr_out;
 
-/* Tuning knobs; 0 selects the default.
+/* Tuning knobs; 0 selects the default.  PB_TUNE in the environment
+ * ("key=value" pairs separated by ',' or ';', keys named as the fields
+ * below, e.g. PB_TUNE="tile_tuples=4096,expand_chunk=512") fills the fields
+ * a call leaves at 0 (also when tune is NULL); a malformed PB_TUNE or an
+ * unknown key makes the symbolic calls return PB_ERR_ARG.
  *   tile_tuples   upper bound on tuples per bin (LDS sort tile): 256..4096;
  *                 default 2048 for a single product, 4096 for a batch
  *   expand_chunk  tuples per expand wave: 256, 512, 1024 or 2048

@@ -178,7 +178,52 @@ int col_bits(int64_t n) {
     return 64 - __builtin_clzll((uint64_t)(n - 1));
 }
 
-pb_status resolve_tune(const pb_tune *t, int default_tile, int *T, int *chunk, int64_t *round_tuples, int *align,
+// PB_TUNE in the environment ("key=value" pairs separated by ',' or ';',
+// keys named as the pb_tune fields) fills the fields the caller left at 0.
+pb_status apply_env_tune(pb_tune *t) {
+    const char *env = getenv("PB_TUNE");
+    if (!env || !*env) return PB_OK;
+    std::string spec(env);
+    size_t pos = 0;
+    while (pos <= spec.size()) {
+        size_t end = spec.find_first_of(",;", pos);
+        if (end == std::string::npos) end = spec.size();
+        std::string item = spec.substr(pos, end - pos);
+        pos = end + 1;
+        const size_t a = item.find_first_not_of(" \t"), z = item.find_last_not_of(" \t");
+        if (a == std::string::npos) continue;
+        item = item.substr(a, z - a + 1);
+        const size_t eq = item.find('=');
+        if (eq == std::string::npos) return fail(PB_ERR_ARG, "PB_TUNE: '%s' is not key=value", item.c_str());
+        auto trim = [](std::string x) {
+            const size_t b = x.find_first_not_of(" \t"), e = x.find_last_not_of(" \t");
+            return b == std::string::npos ? std::string() : x.substr(b, e - b + 1);
+        };
+        const std::string key = trim(item.substr(0, eq)), val = trim(item.substr(eq + 1));
+        char *stop = nullptr;
+        const long long v = strtoll(val.c_str(), &stop, 10);
+        if (val.empty() || !stop || *stop) return fail(PB_ERR_ARG, "PB_TUNE: '%s' is not an integer", val.c_str());
+        auto fill32 = [&](int32_t &f) -> pb_status {
+            if (v < INT32_MIN || v > INT32_MAX) return fail(PB_ERR_ARG, "PB_TUNE: %s out of range", key.c_str());
+            if (f == 0) f = (int32_t)v;
+            return PB_OK;
+        };
+        if (key == "tile_tuples") PB_TRY(fill32(t->tile_tuples));
+        else if (key == "expand_chunk") PB_TRY(fill32(t->expand_chunk));
+        else if (key == "run_align") PB_TRY(fill32(t->run_align));
+        else if (key == "row_count") PB_TRY(fill32(t->row_count));
+        else if (key == "convert") PB_TRY(fill32(t->convert));
+        else if (key == "deterministic") PB_TRY(fill32(t->deterministic));
+        else if (key == "round_tuples") {
+            if (t->round_tuples == 0) t->round_tuples = (int64_t)v;
+        } else {
+            return fail(PB_ERR_ARG, "PB_TUNE: unknown key '%s'", key.c_str());
+        }
+    }
+    return PB_OK;
+}
+
+pb_status resolve_tune(const pb_tune *user, int default_tile, int *T, int *chunk, int64_t *round_tuples, int *align,
                        int *rowcount, int *convert, int *det) {
     *T = default_tile;
     *chunk = kDefaultChunk;
@@ -187,7 +232,10 @@ pb_status resolve_tune(const pb_tune *t, int default_tile, int *T, int *chunk, i
     *rowcount = 0;
     *convert = 1;
     *det = 0;
-    if (!t) return PB_OK;
+    pb_tune eff{};
+    if (user) eff = *user;
+    PB_TRY(apply_env_tune(&eff));
+    const pb_tune *t = &eff;
     if (t->deterministic != 0 && t->deterministic != 1) return fail(PB_ERR_ARG, "deterministic must be 0 or 1");
     *det = t->deterministic;
     if (*det && t->convert == 2) return fail(PB_ERR_ARG, "deterministic mode takes convert 0 or 1");

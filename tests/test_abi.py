@@ -216,3 +216,28 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         B.lib()
+
+
+def test_env_tune_fills_unset_fields(lib, monkeypatch):
+    """PB_TUNE fills the tuning fields a call leaves at 0: row_count=1
+    (device atomics) changes the symbolic workspace size, an explicit
+    row_count in the call wins over it, and a malformed value or an unknown
+    key is PB_ERR_ARG."""
+    a, b = _fake(1000, 500, 3000), _fake(500, 700, 3000)
+    rc, auto = _symbolic(lib, a, b)
+    assert rc == 0
+    t1 = B.PbTune()
+    t1.row_count = 1
+    rc, atomics = _symbolic(lib, a, b, tune=ctypes.byref(t1))
+    assert rc == 0 and atomics != auto
+    monkeypatch.setenv("PB_TUNE", " row_count = 1 ; tile_tuples=4096")
+    assert _symbolic(lib, a, b) == (0, atomics)
+    t2 = B.PbTune()
+    t2.row_count = 2
+    assert _symbolic(lib, a, b, tune=ctypes.byref(t2)) == (0, auto)
+    for bad in ("row_count", "row_count=x", "bogus=1", "tile_tuples=100", "deterministic=1,row_count=1"):
+        monkeypatch.setenv("PB_TUNE", bad)
+        rc, _ = _symbolic(lib, a, b)
+        assert B.STATUS_NAMES[rc] == "PB_ERR_ARG", bad
+    monkeypatch.setenv("PB_TUNE", "")
+    assert _symbolic(lib, a, b) == (0, auto)
