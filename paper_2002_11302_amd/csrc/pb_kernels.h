@@ -1154,8 +1154,10 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, int64_t nchunks) {
 // ConvertCSR, part 1: entries per row of C.  A bin's tuples are contiguous
 // and carry their row inside the bin in the key, so nnz(C(r,:)) is the
 // number of distinct keys with r's row bits.  One workgroup per bin inserts the
-// bin's keys into an LDS hash set (open addressing, linear probing); once
-// every key is in, each occupied slot adds one to its key's row.  Only keys
+// bin's keys into an LDS hash set (open addressing, linear probing); a bin
+// of at most 256 rows credits each newly inserted key to its row (one LDS
+// add per same-row segment of a wave), a bin of more rows lets each
+// occupied slot add one to its key's row once every key is in.  Only keys
 // are read.
 struct CountArgs {
     const int32_t *binrow0;
@@ -1181,6 +1183,8 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
     static_assert(TS >= TMAX, "the row counters reuse the table");
     __shared__ uint32_t table[TS];
     uint32_t *rowcnt = table;  // after the table has been read back
+    constexpr int kSmallRows = 256;
+    __shared__ uint32_t rowcnt_small[kSmallRows];
     if (a.nbins) {
         const uint64_t nb = *a.nbins;
         if (blockIdx.x == 0 && threadIdx.x == 0 && nb > gridDim.x) atomic_or_agent(a.err, (uint32_t)kErrGrid);
@@ -1214,7 +1218,11 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
         kr[i] = gk[(int64_t)(p < N ? p : N - 1) * ks];
     }
     for (int x = threadIdx.x; x < TS; x += BLOCK) table[x] = EMPTY;
+    const bool small = nrows <= kSmallRows;
+    if (small)
+        for (int x = threadIdx.x; x < nrows; x += BLOCK) rowcnt_small[x] = 0;
     __syncthreads();
+    uint32_t fresh = 0;  // bit i: key i entered the set by this thread's swap
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const uint32_t key = kr[i];
@@ -1223,10 +1231,39 @@ __global__ __launch_bounds__(BLOCK) void k_row_nnz(CountArgs a) {
             uint32_t h = (key * 0x9E3779B1u) >> (32 - LOG_TS);
             while (true) {
                 const uint32_t old = atomicCAS(&table[h], EMPTY, key);
+                if (old == EMPTY) fresh |= 1u << i;
                 if (old == EMPTY || old == key) break;
                 h = (h + 1) & (TS - 1);
             }
         }
+    }
+    if (small) {
+        // Bins of at most kSmallRows rows: each key that entered the set
+        // (exactly one lane per distinct key) counts for its row.  A wave's
+        // consecutive lanes hold consecutive tuples, mostly of one run (one
+        // row), so each segment of lanes with the same row adds its new
+        // keys to the row with one LDS update, after every lane's inserts
+        // are done (the wave is converged here).
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int p = i * BLOCK + threadIdx.x;
+            const bool real = p < N && kr[i] != kSentinel;
+            const uint32_t row = real ? (cb < 32 ? (kr[i] >> cb) : 0u) : 0xffffffffu;
+            const uint64_t fm = ballot(((fresh >> i) & 1u) != 0);
+            const uint32_t lane = lane_id();
+            const uint32_t prev = __shfl_up(row, 1u, kWave);
+            const uint64_t heads = ballot(lane == 0 || prev != row);
+            const uint64_t above = heads & ~((2ull << lane) - 1ull);
+            const uint32_t end = above ? (uint32_t)__builtin_ctzll(above) : (uint32_t)kWave;
+            if (((heads >> lane) & 1ull) && row != 0xffffffffu) {
+                const uint64_t seg = (end >= 64u ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
+                const uint32_t c = (uint32_t)__builtin_popcountll(fm & seg);
+                if (c) atomicAdd(&rowcnt_small[row], c);
+            }
+        }
+        __syncthreads();
+        for (int x = threadIdx.x; x < nrows; x += BLOCK) a.rownnz[row0 - a.row_base + x] = rowcnt_small[x];
+        return;
     }
     __syncthreads();
     // Slots hold the bin's distinct keys in hash order, so neighbouring
