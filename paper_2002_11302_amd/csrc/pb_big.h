@@ -24,7 +24,7 @@
 namespace pb {
 
 constexpr int kBigChunk = 65536;  // tuples of a wide row per partition workgroup
-constexpr int kBigSub = 8192;     // tuples staged in LDS per partition step (one 1024-thread workgroup per CU)
+constexpr int kBigSub = 8192;     // tuples staged in LDS per partition step (one 512-thread workgroup per CU)
 constexpr int kMaxLogWin = 10;    // at most 1024 windows per wide row
 constexpr int kDenseBits = 12;    // dense accumulator: 4096 columns
 

@@ -885,8 +885,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
                                   BinDst{L.vrowtab, L.vbinrow0, L.vbinoff, L.Rv, rd.nvirt, (uint64_t)p->Tv, L.vinfo,
                                          L.dense},
                                   L.st_vb, &L.tickets[3], L.err, st, "virtual bin scan"));
-        if (f64) hipLaunchKernelGGL((k_big_scatter<1024, double>), dim3((unsigned)rd.nchunks), dim3(1024), 0, st, ba);
-        else hipLaunchKernelGGL((k_big_scatter<1024, float>), dim3((unsigned)rd.nchunks), dim3(1024), 0, st, ba);
+        if (f64) hipLaunchKernelGGL((k_big_scatter<512, double>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
+        else hipLaunchKernelGGL((k_big_scatter<512, float>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
         PB_LAUNCHED("wide-row scatter");
     }
     DenseArgs da{L.dense, &L.vinfo->noversize, L.Rv, L.keys2, L.vals2, p->wbits, p->lognwin, L.rownnz_v,
