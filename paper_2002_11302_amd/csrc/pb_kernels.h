@@ -957,7 +957,7 @@ __device__ __forceinline__ void expand_flat(const int64_t *__restrict__ F, const
                                             const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
                                             int64_t flop, int64_t slot0, int align, int64_t kb, int nc, int64_t t0,
                                             int64_t t1) {
-    constexpr int U = 4;
+    constexpr int U = 2;
     constexpr int GS = U * kWave;  // tuples per group
     const int lane = (int)lane_id();
     // one column per lane: where its slots start, B's row, A's column
@@ -1045,7 +1045,7 @@ __device__ __forceinline__ void expand_column(const int64_t *__restrict__ F, con
                                               const TupleArr<VT> tup, uint32_t *__restrict__ err, int cb,
                                               int64_t flop, int64_t slot0, int align, int64_t k, int64_t t0,
                                               int64_t t1) {
-    constexpr int U = 4;
+    constexpr int U = 2;
     constexpr int GS = U * kWave;
     const uint32_t lane = lane_id();
     const int64_t Fk = F[k];
