@@ -728,8 +728,8 @@ def summarize_profiles(src: str, out_dir: str, command: str, pmc_command: str) -
     def short(name):
         for key in ("k_expand", "k_sort_compress_fused", "k_sort_compress", "k_row_nnz", "k_rowflop",
                     "k_bucket_hist", "k_bucket_scatter", "k_bucket_count", "k_bucket_dest", "k_bucket_offsets",
-                    "k_entry_dest", "k_bin_max", "k_chained_scan", "k_chunk_start", "k_copy16", "k_fill_u32",
-                    "k_pack"):
+                    "k_entry_dest", "k_bin_max", "k_scan_tiles", "k_scan_apply", "k_chunk_start", "k_copy16",
+                    "k_fill_u32", "k_pack"):
             if key in name:
                 prec = "f32c" if "float" in name else ("f64" if "double" in name else "")
                 return f"{key}<{prec}>" if prec else key

@@ -118,8 +118,9 @@ typedef struct {
  *                 scan over the rows gives the pointers, before the sort;
  *                 2 = fused into the sort (each bin counts its distinct keys
  *                 and takes the entries before it from the earlier bins by a
- *                 decoupled look-back; measured slower, because each bin
- *                 waits for the counts of the bins before it); 0 = 1.  C is
+ *                 decoupled look-back over bins taken in ticket order;
+ *                 measured slower: the bins' tickets, all taken from one
+ *                 device-wide counter, serialise); 0 = 1.  C is
  *                 the same either way.
  *   deterministic 1 = bit-identical C on every call with the same inputs and
  *                 tuning (Section 3.4's bins summed in a fixed order): the

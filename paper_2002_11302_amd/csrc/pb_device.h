@@ -168,14 +168,6 @@ __device__ uint64_t resolve_prefix_wave(uint64_t *status, int64_t tile, uint64_t
     return acc;
 }
 
-// Publish the tile's aggregate (tile 0: its inclusive prefix) and resolve
-// its exclusive prefix: the whole look-back of a chained scan's tile.
-template <class Op>
-__device__ uint64_t look_back_wave(uint64_t *status, int64_t tile, uint64_t agg, uint32_t *err) {
-    if (lane_id() == 0) atomic_store_agent(&status[tile], (tile == 0 ? kFlagPrefix : kFlagAgg) | agg);
-    return resolve_prefix_wave<Op>(status, tile, agg, err);
-}
-
 // largest i in [lo, hi) with a[i] <= x, given a[lo] <= x (a non-decreasing)
 template <class T>
 __device__ __forceinline__ int64_t last_le(const T *a, int64_t lo, int64_t hi, T x) {

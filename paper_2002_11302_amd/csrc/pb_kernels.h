@@ -35,56 +35,77 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// Single-pass chained scan (decoupled look-back).  Tiles are claimed in
-// ticket order; thread t of a tile owns IPT consecutive elements.
-// Src(i) -> element payload; Dst(i, exclusive, element) stores results;
-// Dst::total(t) receives the grand total (called by the owner of the last
-// element); Dst::side(i, e) -> value max-reduced per tile and handed to
-// Dst::side_commit.
-template <int BLOCK, int IPT, class Op, class Src, class Dst>
-__global__ __launch_bounds__(BLOCK) void k_chained_scan(int64_t n, Src src, Dst dst, uint64_t *status,
-                                                        uint32_t *ticket, uint32_t *err) {
+// Scan in two launches (reduce, then scan): k_scan_tiles writes each tile's
+// total, k_scan_apply combines the totals of the tiles before its own (in
+// tile order) and scans its tile.  No tile waits for another, so nothing
+// depends on the order in which workgroups start; a single-pass scan would
+// need every tile to take a ticket from one device-wide counter, and on
+// this chip's eight XCDs those tickets serialise.  Thread t of a tile owns
+// IPT consecutive elements.  Src(i) -> element payload; Dst(i, exclusive,
+// element) stores results; Dst::total(t) receives the grand total (called by
+// the owner of the last element); Dst::side(i, e) -> value max-reduced per
+// tile and handed to Dst::side_commit.  Op may be non-commutative: every
+// combination is made in element order.
+template <int BLOCK, int IPT, class Op, class Src>
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(int64_t n, Src src, uint64_t *part) {
     constexpr int NW = BLOCK / kWave;
-    __shared__ uint64_t s_tmp[NW + 2];
+    __shared__ uint64_t s_tmp[NW + 1];
+    const int64_t base = blockIdx.x * (int64_t)(BLOCK * IPT) + (int64_t)threadIdx.x * IPT;
+    uint64_t e[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) e[j] = base + j < n ? src(base + j) : Op::identity();
+    uint64_t local = Op::identity();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) local = Op::combine(local, e[j]);
+    uint64_t tile_total;
+    block_excl_scan<BLOCK, Op>(local, s_tmp, tile_total);
+    if (threadIdx.x == 0) part[blockIdx.x] = tile_total;
+}
+
+template <int BLOCK, int IPT, class Op, class Src, class Dst>
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(int64_t n, Src src, Dst dst, const uint64_t *part) {
+    constexpr int NW = BLOCK / kWave;
+    __shared__ uint64_t s_tmp[NW + 1];
     __shared__ uint64_t s_side[NW];
-    __shared__ int64_t s_tile;
-    if (threadIdx.x == 0) s_tile = atomic_add_agent(ticket, 1u);
-    __syncthreads();
-    const int64_t tile = s_tile;
+    const int64_t tile = blockIdx.x;
     const int64_t base = tile * (int64_t)(BLOCK * IPT) + (int64_t)threadIdx.x * IPT;
     uint64_t e[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) e[j] = base + j < n ? src(base + j) : Op::identity();
+    // the tiles before this one: thread t combines a consecutive range of
+    // their totals, the block combines the threads in order
+    const int64_t per = (tile + BLOCK - 1) / BLOCK;
+    const int64_t t0 = (int64_t)threadIdx.x * per;
+    const int64_t t1 = t0 + per < tile ? t0 + per : tile;
+    uint64_t pre = Op::identity();
+    for (int64_t x = t0; x < t1; ++x) pre = Op::combine(pre, part[x]);
+    uint64_t before;
+    block_excl_scan<BLOCK, Op>(pre, s_tmp, before);
     uint64_t local = Op::identity();
     uint64_t side = 0;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t i = base + j;
-        e[j] = i < n ? src(i) : Op::identity();
         if (i < n) {
-            uint64_t sv = dst.side(i, e[j]);
+            const uint64_t sv = dst.side(i, e[j]);
             side = sv > side ? sv : side;
         }
         local = Op::combine(local, e[j]);
     }
-    // tile max of the side values
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) {
-        uint64_t o = __shfl_xor(side, d, kWave);
+        const uint64_t o = __shfl_xor(side, d, kWave);
         side = o > side ? o : side;
     }
     if (lane_id() == 0) s_side[threadIdx.x / kWave] = side;
     uint64_t tile_total;
-    const uint64_t texcl = block_excl_scan<BLOCK, Op>(local, s_tmp, tile_total);
-    if (threadIdx.x < kWave) {
-        if (threadIdx.x == 0) {
-            uint64_t mx = 0;
-            for (int i = 0; i < NW; ++i) mx = s_side[i] > mx ? s_side[i] : mx;
-            dst.side_commit(mx);
-        }
-        const uint64_t ex = look_back_wave<Op>(status, tile, tile_total, err);
-        if (threadIdx.x == 0) s_tmp[NW + 1] = ex;
+    const uint64_t texcl = block_excl_scan<BLOCK, Op>(local, s_tmp, tile_total);  // has barriers
+    if (threadIdx.x == 0) {
+        uint64_t mx = 0;
+        for (int w = 0; w < NW; ++w) mx = s_side[w] > mx ? s_side[w] : mx;
+        dst.side_commit(mx);
     }
-    __syncthreads();
-    uint64_t run = Op::combine(s_tmp[NW + 1], texcl);
+    uint64_t run = Op::combine(before, texcl);
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int64_t i = base + j;

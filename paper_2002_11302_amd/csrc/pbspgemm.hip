@@ -324,8 +324,7 @@ namespace {
 
 struct SymLayout {
     SymInfo *info;
-    uint32_t *tickets;
-    uint64_t *stF, *stR, *stB;
+    uint64_t *stF, *stR, *stB;  // scan tile totals
     uint64_t *R;
     int64_t *F;
     RowTab *rowtab;
@@ -393,7 +392,6 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
     L.cpw = bs.cpw;
     // zeroed region first
     L.info = cv.take<SymInfo>(1);
-    L.tickets = cv.take<uint32_t>(4);
     L.stF = cv.take<uint64_t>(ceil_div(k, kScanTile) + 1);
     L.stR = cv.take<uint64_t>(ceil_div(m, kScanTile) + 1);
     L.stB = cv.take<uint64_t>(ceil_div(m, kScanTile) + 1);
@@ -436,8 +434,8 @@ SymLayout sym_layout(void *base, int64_t m, int64_t k, int64_t nnza, int64_t nnz
 }
 
 struct NumLayout {
-    uint32_t *ticket, *err, *sticket;
-    uint64_t *status, *sstatus;
+    uint32_t *err, *sticket;  // sticket: fused ConvertCSR's bin order
+    uint64_t *status, *sstatus;  // row-pointer scan tile totals; fused ConvertCSR's bin status
     int32_t *kstart;
     uint32_t *rownnz;
     OutDesc *outs;
@@ -449,9 +447,8 @@ struct NumLayout {
 NumLayout num_layout(void *base, const pb_plan *p) {
     Carver cv(base);
     NumLayout L{};
-    L.ticket = cv.take<uint32_t>(3);
-    L.err = L.ticket + 1;
-    L.sticket = L.ticket + 2;
+    L.err = cv.take<uint32_t>(2);
+    L.sticket = L.err + 1;
     L.status = cv.take<uint64_t>(ceil_div(p->m, kScanTile) + 1);
     L.sstatus = cv.take<uint64_t>((int64_t)p->h.nbins + 1);
     L.zero_bytes = cv.mark();
@@ -481,13 +478,16 @@ pb_status fill_zero(void *p, size_t bytes, hipStream_t st) {
     return PB_OK;
 }
 
+// part: ceil(n / kScanTile) words of scratch for the tile totals.
 template <class Op, class Src, class Dst>
-pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *ticket, uint32_t *err, hipStream_t st,
-                      const char *name) {
+pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *part, hipStream_t st, const char *name) {
     if (n <= 0) return PB_OK;
     const int64_t tiles = ceil_div(n, kScanTile);
-    hipLaunchKernelGGL((k_chained_scan<kScanBlock, kScanIpt, Op, Src, Dst>), dim3((unsigned)tiles), dim3(kScanBlock),
-                       0, st, n, src, dst, status, ticket, err);
+    hipLaunchKernelGGL((k_scan_tiles<kScanBlock, kScanIpt, Op, Src>), dim3((unsigned)tiles), dim3(kScanBlock), 0, st, n,
+                       src, part);
+    PB_LAUNCHED(name);
+    hipLaunchKernelGGL((k_scan_apply<kScanBlock, kScanIpt, Op, Src, Dst>), dim3((unsigned)tiles), dim3(kScanBlock), 0,
+                       st, n, src, dst, (const uint64_t *)part);
     PB_LAUNCHED(name);
     return PB_OK;
 }
@@ -496,12 +496,11 @@ pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *status, uint32_t *t
 pb_status run_row_bins(pb_plan *p, const SymLayout &L, hipStream_t st) {
     const int64_t m = p->m;
     if (m <= 0) return PB_OK;
-    PB_TRY(launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(p->T / 2), L.info}, L.stR,
-                              &L.tickets[1], &L.info->err, st, "row scan"));
+    PB_TRY(launch_scan<SumOp>(m, RowFlopSrc{L.R}, RowFlopDst{L.R, m, (uint64_t)(p->T / 2), L.info}, L.stR, st,
+                              "row scan"));
     PB_TRY(launch_scan<BinOp>(
         m, BinSrc{L.R, L.info, (uint64_t)p->T, 32 - p->cb, p->count > 1 ? L.prob_row0 : nullptr, p->count, -1},
-        BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, &L.tickets[2],
-        &L.info->err, st, "bin scan"));
+        BinDst{L.rowtab, L.binrow0, L.binoff, L.R, m, (uint64_t)p->T, L.info, nullptr}, L.stB, st, "bin scan"));
     hipLaunchKernelGGL(k_bin_max, dim3((unsigned)std::min<int64_t>(ceil_div(m, 256), 512)), dim3(256), 0, st, L.binoff,
                        m, L.info);
     PB_LAUNCHED("largest bin");
@@ -514,8 +513,8 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
                        hipStream_t st) {
     const int64_t m = p->m, k = p->k;
     if (k > 0) {
-        PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp, p->align}, ColFlopDst{{}, L.F, k, L.info}, L.stF,
-                                  &L.tickets[0], &L.info->err, st, "flop scan"));
+        PB_TRY(launch_scan<SumOp>(k, ColFlopSrc{acp, brp, p->align}, ColFlopDst{{}, L.F, k, L.info}, L.stF, st,
+                                  "flop scan"));
         if (p->rowcount == 2) {
             RowBucketArgs ra{};
             ra.K = k;
@@ -549,8 +548,8 @@ pb_status run_symbolic(pb_plan *p, const SymLayout &L, const int64_t *acp, const
             const dim3 grid((unsigned)L.ngrp), block(kBucketBlock);
             hipLaunchKernelGGL(k_bucket_hist<kBucketBlock>, grid, block, lds, st, ra);
             PB_LAUNCHED("bucket histogram");
-            PB_TRY(launch_scan<SumOp>(nh, HistSrc{L.hist}, HistDst{{}, L.hist, nh}, L.stH, &L.tickets[3],
-                                      &L.info->err, st, "bucket scan"));
+            PB_TRY(launch_scan<SumOp>(nh, HistSrc{L.hist}, HistDst{{}, L.hist, nh}, L.stH, st,
+                                      "bucket scan"));
             hipLaunchKernelGGL(k_bucket_scatter<kBucketBlock>, grid, block, lds, st, ra);
             PB_LAUNCHED("bucket scatter");
             if (p->det) hipLaunchKernelGGL(k_bucket_count_det<512>, dim3((unsigned)L.nbkt), dim3(512), 0, st, ra, m);
@@ -623,8 +622,8 @@ pb_status ensure_pinned(pb_plan *p, size_t bytes);
 // first; the wide-row tables (bigs, bige, cpre, bigr) are one block, in the
 // order of the pinned staging copy.
 struct RoundLayout {
-    uint32_t *tickets;  // [0] rows, [1] columns, [2] virtual rows, [3] virtual bins, [5] sorted bins
     uint32_t *err;
+    uint32_t *sort_ticket;  // fused ConvertCSR: bin order
     SymInfo *rinfo, *vinfo;
     uint64_t *st_rows, *st_cols, *st_v, *st_vb, *st_sort;
     uint32_t *cnt_v, *cur_v;
@@ -667,8 +666,8 @@ RoundLayout round_layout(void *base, const pb_plan *p, const pb_plan::Round &rd)
     const bool partial = rd.r0 > 0 || rd.r1 < p->m;
     const int64_t nrows = rd.r1 - rd.r0;
     const int vb = p->prec == PB_F64 ? 8 : 4;
-    L.tickets = cv.take<uint32_t>(6);
-    L.err = L.tickets + 4;
+    L.err = cv.take<uint32_t>(2);
+    L.sort_ticket = L.err + 1;
     L.rinfo = cv.take<SymInfo>(1);
     L.vinfo = cv.take<SymInfo>(1);
     L.st_rows = cv.take<uint64_t>(ceil_div(nrows, kScanTile) + 1);
@@ -838,8 +837,8 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
             hipLaunchKernelGGL(k_round_cols, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, st, K, A->ptr, A->idx,
                                B->ptr, (int32_t)rd.r0, (int32_t)rd.r1, p->align, L.astart, L.colflop);
             PB_LAUNCHED("round columns");
-            PB_TRY(launch_scan<SumOp>(K, U64Src{L.colflop}, ColFlopDst{{}, L.F, K, L.rinfo}, L.st_cols,
-                                      &L.tickets[1], L.err, st, "round flop scan"));
+            PB_TRY(launch_scan<SumOp>(K, U64Src{L.colflop}, ColFlopDst{{}, L.F, K, L.rinfo}, L.st_cols, st,
+                                      "round flop scan"));
             F = L.F;
             astart = L.astart;
         }
@@ -879,12 +878,12 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         hipLaunchKernelGGL(k_big_hist<512>, dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
         PB_LAUNCHED("wide-row histogram");
         PB_TRY(launch_scan<SumOp>(rd.nvirt, U32Src{L.cnt_v}, RowFlopDst{L.Rv, rd.nvirt, (uint64_t)(p->Tv / 2), L.vinfo},
-                                  L.st_v, &L.tickets[2], L.err, st, "virtual row scan"));
+                                  L.st_v, st, "virtual row scan"));
         PB_TRY(launch_scan<BinOp>(rd.nvirt,
                                   BinSrc{L.Rv, L.vinfo, (uint64_t)p->Tv, 32 - p->wbits, nullptr, 0, p->lognwin},
                                   BinDst{L.vrowtab, L.vbinrow0, L.vbinoff, L.Rv, rd.nvirt, (uint64_t)p->Tv, L.vinfo,
                                          L.dense},
-                                  L.st_vb, &L.tickets[3], L.err, st, "virtual bin scan"));
+                                  L.st_vb, st, "virtual bin scan"));
         if (f64) hipLaunchKernelGGL((k_big_scatter<512, double>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
         else hipLaunchKernelGGL((k_big_scatter<512, float>), dim3((unsigned)rd.nchunks), dim3(512), 0, st, ba);
         PB_LAUNCHED("wide-row scatter");
@@ -929,7 +928,7 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
         }
         if (!fused && nrows > 0)
             PB_TRY(launch_scan<SumOp>(nrows, RowNnzSrc{L.rownnz}, RowPtrDst{{}, rowptr_out, nrows, rowptr_base},
-                                      L.st_rows, &L.tickets[0], L.err, st, "row pointer scan"));
+                                      L.st_rows, st, "row pointer scan"));
     }
     {
         ProfScope ps(st, 2);
@@ -951,7 +950,7 @@ pb_status run_round(pb_plan *p, const pb_plan::Round &rd, void *ws, const pb_csx
             sa.slot0 = rd.slot0;
             sa.row_base = rd.r0;
             sa.fused = fused ? 1 : 0;
-            sa.ticket = &L.tickets[5];
+            sa.ticket = L.sort_ticket;
             sa.status = L.st_sort;
             sa.bignnz = L.rownnz;
             sa.rowptr_base = rowptr_base;
@@ -1065,11 +1064,11 @@ pb_status run_numeric(pb_plan *p, const NumLayout &L, const int64_t *acp, const 
             PB_LAUNCHED("row counts");
             if (batch) {
                 PB_TRY(launch_scan<SegSumOp>(p->m, SegRowNnzSrc{L.rownnz, p->prob_row0, p->count},
-                                             SegRowPtrDst{{}, L.outs, p->prob_row0, p->count}, L.status, L.ticket, L.err,
-                                             st, "row pointer scan"));
+                                             SegRowPtrDst{{}, L.outs, p->prob_row0, p->count}, L.status, st,
+                                             "row pointer scan"));
             } else {
-                PB_TRY(launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m, nullptr}, L.status, L.ticket,
-                                          L.err, st, "row pointer scan"));
+                PB_TRY(launch_scan<SumOp>(p->m, RowNnzSrc{L.rownnz}, RowPtrDst{{}, C->rowptr, p->m, nullptr}, L.status, st,
+                                          "row pointer scan"));
             }
         }
         SortArgs sa{};
