@@ -323,6 +323,8 @@ def bench_batched(pb, torch, steps, warmup):
         best = autotune.tune(run, key, log=log)
         tune = {"tile_tuples": best["tile_tuples"], "expand_chunk": best["expand_chunk"]}
         sym, plan, ws = prepared(tune)
+        if outs is None:  # the tuning came from the cache, nothing ran yet
+            outs = _outputs(torch, pairs, plan.flops, prec)
         nnz = pb.spgemm_batched(plan, pairs, ws, outs, sync=True)
         tot_flop = int(sum(plan.flops))
         tot_nnz = int(sum(nnz))
