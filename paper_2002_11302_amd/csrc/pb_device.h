@@ -9,7 +9,7 @@ constexpr int kWave = 64;
 
 // Device-side error bits, OR-ed into a status word in the workspace.
 enum : uint32_t {
-    kErrSpin = 1u,      // a look-back wait gave up (should never happen)
+    kErrSpin = 1u,      // a look-back wait of the fused ConvertCSR gave up (should never happen)
     kErrBinOverflow = 2u,  // an expand append ran past its bin (inconsistent inputs)
     kErrCapacity = 4u,  // C had less room than nnz(C)
     kErrTile = 8u,      // a bin larger than the sort tile reached the sort kernel

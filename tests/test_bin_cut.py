@@ -1,6 +1,6 @@
 """The bin-cut rule of the symbolic step, restated on the host (CPU only).
 
-The device computes it inside a chained scan; this file states the rule in
+The device computes it inside a scan over the rows; this file states the rule in
 plain numpy and checks the two bounds the packed key relies on, on
 adversarial row-flop profiles: every bin of normal rows holds fewer than T
 tuples, and at most 2^rowbits - 1 rows, so that the row part of a key,
