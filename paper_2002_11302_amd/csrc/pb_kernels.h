@@ -1924,12 +1924,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2
     __syncthreads();
     // run heads (first tuple of each key), counted per wave
     uint32_t wrun = 0;
-    uint32_t hr[IPT];
+    uint32_t hr[IPT], kc[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
         bool head = false;
-        if (p < Nr) head = (p == 0) || (keyA[p] != keyA[p - 1]);
+        kc[i] = kSentinel;
+        if (p < Nr) {
+            kc[i] = keyA[p];
+            head = (p == 0) || (kc[i] != keyA[p - 1]);
+        }
         const uint64_t hm = ballot(head);
         hr[i] = head ? (wrun + popc_lt(hm)) : 0xffffffffu;
         wrun += popc64(hm);
@@ -1952,7 +1956,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TMAX <= 2
         for (int i = 0; i < IPT; ++i) {
             const int p = (int)w * kWave * IPT + i * kWave + (int)lane;
             const int pc = p < Nr ? p : Nr - 1;
-            hk[i] = keyA[pc];
+            hk[i] = kc[i];
             hs[i] = slotA[pc];
             hn[i] = p + 1 < Nr ? keyA[p + 1] : kSentinel;
         }
