@@ -1,10 +1,10 @@
 """GPU parity for the full-size R-MAT product C = A*A (scale 20, edge
 factor 16): 7e10 tuples and 2.4e10 entries of C, so the product runs in
 row-range rounds into one reused buffer.  The oracle computes sampled rows
-(the heaviest hub rows and random rows) and a block of consecutive rows at
-the start of the lightest round (up to 3e8 multiplications, row pointers
-included) exactly; every round is also checked for properties that hold at
-any size."""
+(the heaviest hub rows and random rows) and the lightest round (every row
+of it while its multiplications stay under 2.5e9, row pointers included)
+exactly; every round is also checked for properties that hold at any
+size."""
 import os
 import sys
 
@@ -50,11 +50,11 @@ _BLOCK = {}
 
 def _block_ref(ac, a, rowflop, r0, r1, nth):
     """Oracle rows [r0, r1') where r1' <= r1 keeps the block's
-    multiplications under 3e8 (at least one row)."""
+    multiplications under 2.5e9 (at least one row)."""
     key = (r0, r1)
     if key not in _BLOCK:
         cum = np.cumsum(rowflop[r0:r1])
-        nrow = max(1, int(np.searchsorted(cum, 3e8, side="right")))
+        nrow = max(1, int(np.searchsorted(cum, 2.5e9, side="right")))
         rows = np.arange(r0, r0 + nrow, dtype=np.int64)
         _say(f"oracle on rows [{r0}, {r0 + nrow}) of the lightest round ({int(cum[nrow - 1])} flop)")
         _BLOCK[key] = (rows, oracle.spgemm_rows(ac, a, rows, nthreads=nth))
@@ -118,7 +118,8 @@ def test_rmat_scale20_rounds(setup, precision):
             assert np.array_equal(ci[g0:g1].cpu().numpy(), bref["idx"]), f"round {r}: columns of the block"
             gv = cv[g0:g1].cpu().numpy().astype(np.float64)
             assert np.all(np.abs(gv - bref["val"]) <= TOL[precision] * bref["absval"]), f"round {r}: block values"
-            _say(f"{precision}: round {r}: block of {brows.size} rows, {g1 - g0} entries equal the oracle")
+            whole = "the whole round" if brows.size == nrows else f"{brows.size} of its {nrows} rows"
+            _say(f"{precision}: round {r}: {whole}, {g1 - g0} entries, equal the oracle")
         if r % 4 == 0:
             _say(f"{precision}: round {r + 1}/{len(fl)} ok")
     assert seen == rows.size
