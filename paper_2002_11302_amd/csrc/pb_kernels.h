@@ -37,7 +37,10 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Scan in two launches (reduce, then scan): k_scan_tiles writes each tile's
 // total, k_scan_apply combines the totals of the tiles before its own (in
-// tile order) and scans its tile.  No tile waits for another, so nothing
+// tile order) and scans its tile.  With many tiles, that combination would
+// grow with the square of the tile count, so k_scan_parts (one workgroup)
+// first turns the totals into exclusive prefixes in place and each tile
+// reads its own.  No tile waits for another, so nothing
 // depends on the order in which workgroups start; a single-pass scan would
 // need every tile to take a ticket from one device-wide counter, and on
 // this chip's eight XCDs those tickets serialise.  Thread t of a tile owns
@@ -62,8 +65,38 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(int64_t n, Src src, uint64
     if (threadIdx.x == 0) part[blockIdx.x] = tile_total;
 }
 
+// Exclusive scan of the tile totals in place, by one workgroup, in chunks
+// of BLOCK * 8 carried in tile order.
+template <int BLOCK, class Op>
+__global__ __launch_bounds__(BLOCK) void k_scan_parts(int64_t tiles, uint64_t *part) {
+    constexpr int NW = BLOCK / kWave;
+    constexpr int PPT = 8;
+    __shared__ uint64_t s_tmp[NW + 1];
+    uint64_t carry = Op::identity();
+    for (int64_t c0 = 0; c0 < tiles; c0 += (int64_t)BLOCK * PPT) {
+        const int64_t base = c0 + (int64_t)threadIdx.x * PPT;
+        uint64_t e[PPT];
+        uint64_t local = Op::identity();
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            e[j] = base + j < tiles ? part[base + j] : Op::identity();
+            local = Op::combine(local, e[j]);
+        }
+        uint64_t tot;
+        uint64_t run = Op::combine(carry, block_excl_scan<BLOCK, Op>(local, s_tmp, tot));  // has barriers
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            if (base + j < tiles) part[base + j] = run;
+            run = Op::combine(run, e[j]);
+        }
+        carry = Op::combine(carry, tot);
+    }
+}
+
+// prefixed: part[t] already holds the combination of the tiles before t.
 template <int BLOCK, int IPT, class Op, class Src, class Dst>
-__global__ __launch_bounds__(BLOCK) void k_scan_apply(int64_t n, Src src, Dst dst, const uint64_t *part) {
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(int64_t n, Src src, Dst dst, const uint64_t *part,
+                                                      int prefixed) {
     constexpr int NW = BLOCK / kWave;
     __shared__ uint64_t s_tmp[NW + 1];
     __shared__ uint64_t s_side[NW];
@@ -72,15 +105,20 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(int64_t n, Src src, Dst ds
     uint64_t e[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) e[j] = base + j < n ? src(base + j) : Op::identity();
-    // the tiles before this one: thread t combines a consecutive range of
-    // their totals, the block combines the threads in order
-    const int64_t per = (tile + BLOCK - 1) / BLOCK;
-    const int64_t t0 = (int64_t)threadIdx.x * per;
-    const int64_t t1 = t0 + per < tile ? t0 + per : tile;
-    uint64_t pre = Op::identity();
-    for (int64_t x = t0; x < t1; ++x) pre = Op::combine(pre, part[x]);
+    // the tiles before this one: their prefix, or (few tiles) thread t
+    // combines a consecutive range of their totals and the block combines
+    // the threads in order
     uint64_t before;
-    block_excl_scan<BLOCK, Op>(pre, s_tmp, before);
+    if (prefixed) {
+        before = part[tile];
+    } else {
+        const int64_t per = (tile + BLOCK - 1) / BLOCK;
+        const int64_t t0 = (int64_t)threadIdx.x * per;
+        const int64_t t1 = t0 + per < tile ? t0 + per : tile;
+        uint64_t pre = Op::identity();
+        for (int64_t x = t0; x < t1; ++x) pre = Op::combine(pre, part[x]);
+        block_excl_scan<BLOCK, Op>(pre, s_tmp, before);
+    }
     uint64_t local = Op::identity();
     uint64_t side = 0;
 #pragma unroll

@@ -53,6 +53,7 @@ pb_status fail(pb_status s, const char *fmt, ...) {
 
 // Kernel shapes.
 constexpr int kScanBlock = 256, kScanIpt = 8, kScanTile = kScanBlock * kScanIpt;
+constexpr int64_t kScanDirect = 4096;  // tiles up to which k_scan_apply sums the earlier totals itself
 constexpr int kSortBlock = 512, kSortTmax = 4096;
 constexpr int kSortBlockSmall = 256, kSortTmaxSmall = 2048;
 constexpr int kCountBlock = 512, kCountBlockSmall = 256;
@@ -486,8 +487,14 @@ pb_status launch_scan(int64_t n, Src src, Dst dst, uint64_t *part, hipStream_t s
     hipLaunchKernelGGL((k_scan_tiles<kScanBlock, kScanIpt, Op, Src>), dim3((unsigned)tiles), dim3(kScanBlock), 0, st, n,
                        src, part);
     PB_LAUNCHED(name);
+    // up to kScanDirect tiles each tile combines the totals before it itself
+    const bool prefixed = tiles > kScanDirect;
+    if (prefixed) {
+        hipLaunchKernelGGL((k_scan_parts<kScanBlock, Op>), dim3(1), dim3(kScanBlock), 0, st, tiles, part);
+        PB_LAUNCHED(name);
+    }
     hipLaunchKernelGGL((k_scan_apply<kScanBlock, kScanIpt, Op, Src, Dst>), dim3((unsigned)tiles), dim3(kScanBlock), 0,
-                       st, n, src, dst, (const uint64_t *)part);
+                       st, n, src, dst, (const uint64_t *)part, prefixed ? 1 : 0);
     PB_LAUNCHED(name);
     return PB_OK;
 }

@@ -5,6 +5,7 @@ are compared against N = |A||B| of each entry (for non-negative inputs N is
 the value itself, so this is the relative error): FP64 within 1e-12, FP32
 tuples with compensated merge within 1e-6.
 """
+import os
 import sys
 
 import numpy as np
@@ -445,3 +446,18 @@ def test_bin_cut_matches_rule(pb, case):
     assert info["nbins"] == starts.size
     assert info["max_bin_tuples"] == int(sizes.max())
     assert info["max_row_flop"] == int(rowflop.max())
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_rows_beyond_direct_scan_limit(pb, precision):
+    """More than 4096 scan tiles of 2048 rows (9.4M rows and columns): the
+    column-flop scan, the row scan, the bin cut (a non-commutative scan)
+    and, for single products, every scan over the rows then go through the
+    one-workgroup pass that turns the tile totals into prefixes.  Whole C
+    against the oracle."""
+    n = (1 << 23) + (1 << 20)
+    _say(f"ER n={n} d=2 A*B ({precision})")
+    a, b = er_problem(n, 2, 71, 72)
+    got = _run(pb, a, b, precision)
+    ref = oracle.spgemm(a, b, nthreads=len(os.sched_getaffinity(0)))
+    _compare(got, ref, precision)
