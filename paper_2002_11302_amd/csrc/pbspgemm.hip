@@ -53,7 +53,7 @@ pb_status fail(pb_status s, const char *fmt, ...) {
 
 // Kernel shapes.
 constexpr int kScanBlock = 256, kScanIpt = 8, kScanTile = kScanBlock * kScanIpt;
-constexpr int64_t kScanDirect = 4096;  // tiles up to which k_scan_apply sums the earlier totals itself
+constexpr int64_t kScanDirect = 1024;  // tiles up to which k_scan_apply sums the earlier totals itself
 constexpr int kSortBlock = 512, kSortTmax = 4096;
 constexpr int kSortBlockSmall = 256, kSortTmaxSmall = 2048;
 constexpr int kCountBlock = 512, kCountBlockSmall = 256;

@@ -450,7 +450,8 @@ def test_bin_cut_matches_rule(pb, case):
 
 @pytest.mark.parametrize("precision", ["f64", "f32c"])
 def test_rows_beyond_direct_scan_limit(pb, precision):
-    """More than 4096 scan tiles of 2048 rows (9.4M rows and columns): the
+    """More than 4096 scan tiles of 2048 rows (9.4M rows and columns), well
+    past the 1024 up to which each tile combines the earlier totals itself: the
     column-flop scan, the row scan, the bin cut (a non-commutative scan)
     and, for single products, every scan over the rows then go through the
     one-workgroup pass that turns the tile totals into prefixes.  Whole C
