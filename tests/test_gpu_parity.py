@@ -449,14 +449,14 @@ def test_bin_cut_matches_rule(pb, case):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32c"])
-def test_rows_beyond_direct_scan_limit(pb, precision):
-    """More than 4096 scan tiles of 2048 rows (9.4M rows and columns), well
-    past the 1024 up to which each tile combines the earlier totals itself: the
-    column-flop scan, the row scan, the bin cut (a non-commutative scan)
-    and, for single products, every scan over the rows then go through the
-    one-workgroup pass that turns the tile totals into prefixes.  Whole C
-    against the oracle."""
-    n = (1 << 23) + (1 << 20)
+@pytest.mark.parametrize("n", [(1 << 21) + 1, (1 << 23) + (1 << 20)])
+def test_rows_beyond_direct_scan_limit(pb, precision, n):
+    """Scans of more than 1024 tiles of 2048 elements (the limit up to which
+    each tile combines the earlier tiles' totals itself): 1025 tiles, the
+    last holding one row, and 4608 tiles (three chunks of the one-workgroup
+    pass that turns the totals into prefixes).  The column-flop scan, the
+    row scan and the bin cut (a non-commutative scan) take that path.  Whole
+    C against the oracle."""
     _say(f"ER n={n} d=2 A*B ({precision})")
     a, b = er_problem(n, 2, 71, 72)
     got = _run(pb, a, b, precision)
