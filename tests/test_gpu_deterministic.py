@@ -8,6 +8,7 @@ C(i,j) left to right over ascending k in double).  So in FP64 the structure
 AND the values must equal the oracle's bit for bit, and in both precisions
 repeated calls, other tiles, run alignments, rounds and batches must give
 the same bits."""
+import os
 import sys
 
 import numpy as np
@@ -145,3 +146,28 @@ def test_wide_rows_refused(pb):
         pb.spgemm(A, B, tune={"deterministic": 1, "tile_tuples": 256})
     assert ei.value.name == "PB_ERR_UNSUPPORTED"
     pb.spgemm(A, B, tune={"tile_tuples": 256})
+
+
+def test_headline_product_bits_equal_oracle(pb):
+    """The benchmark's product (ER n=2^20, d=16, C = A*B: 2.7e8
+    multiplications), all of C: in the fixed order its FP64 values are the
+    oracle's bit for bit."""
+    _say("ER 2^20 d16 A*B, fixed order, all of C")
+    a, b = er_problem(1 << 20, 16, 2, 3)
+    got = _run(pb, a, b)
+    _same(got, oracle.spgemm(a, b, nthreads=len(os.sched_getaffinity(0))), "ER 2^20 d16")
+
+
+def test_amg_128_chain_bits_equal_oracle(pb):
+    """The AMG chain of the benchmark (7-point Laplacian 128^3): T = A*P and
+    Ac = R*T, both bit-equal to the oracle's chain in the fixed order."""
+    _say("amg 128^3 chain, fixed order")
+    A, P = amg_problem(128)
+    nth = len(os.sched_getaffinity(0))
+    a_csc = Csx(A.nrows, A.ncols, A.ptr, A.idx, A.val, "csc")
+    t_ref = oracle.spgemm(a_csc, P, nthreads=nth)
+    t = _run(pb, a_csc, P)
+    _same(t, t_ref, "T = A*P")
+    r_csc = Csx(P.ncols, P.nrows, P.ptr, P.idx, P.val, "csc")
+    t_csr = Csx(A.nrows, P.ncols, t["rowptr"], t["colidx"], t["val"], "csr")
+    _same(_run(pb, r_csc, t_csr), oracle.spgemm(r_csc, t_csr, nthreads=nth), "Ac = R*T")
