@@ -783,6 +783,63 @@ def summarize_profiles(src: str, out_dir: str, command: str, pmc_command: str) -
         f.write("\n")
 
 
+def summarize_rmat_counters(src: str, out_path: str, pmc_command: str) -> None:
+    """Write the R-MAT product's HBM traffic per kernel and product from two
+    rocprofv3 counter runs (FETCH_SIZE then WRITE_SIZE in src/fetch and
+    src/write) of `bench.py --quick --rmat`, scaled by what the counters read
+    for the copy kernel.  That run does, per precision, four products (one
+    to count nnz(C), one warm-up, two timed): kernels templated on the value
+    type ran in 4 products, the others in 8 (the ER n=2^20 steps that run
+    first add well under 1 % of these bytes)."""
+    import csv
+    import glob
+
+    def per_kernel(kind):
+        files = glob.glob(os.path.join(src, kind, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise FileNotFoundError(f"no counter_collection.csv under {src}/{kind}")
+        acc, n = {}, {}
+        with open(files[0]) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") != kind.upper() + "_SIZE":
+                    continue
+                name = r["Kernel_Name"]
+                key = name.split("(")[0].replace("void ", "").strip()
+                if "double" in name:
+                    key += " <f64>"
+                elif "float" in name:
+                    key += " <f32c>"
+                acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+                n[key] = n.get(key, 0) + 1
+        return acc, n
+
+    (fetch, nf), (write, _) = per_kernel("fetch"), per_kernel("write")
+    copy_bytes = 4 << 30
+    copy = [k for k in fetch if "k_copy16" in k][0]
+    f_scale = copy_bytes / (fetch[copy] / nf[copy] * 1024.0)
+    w_scale = copy_bytes / (write[copy] / nf[copy] * 1024.0)
+    lines = ["# HBM traffic per R-MAT product (scale 20, ef 16, C = A*A in 17 rounds) from rocprofv3 counters",
+             f"# (FETCH_SIZE and WRITE_SIZE summed over a kernel's dispatches, divided by the products that ran it),",
+             f"# scaled by the copy kernel: fetch x{f_scale:.3f}, write x{w_scale:.3f}",
+             "# commands: " + pmc_command.replace("{COUNTER}", "FETCH_SIZE").replace("{KIND}", "fetch"),
+             "#      and: " + pmc_command.replace("{COUNTER}", "WRITE_SIZE").replace("{KIND}", "write"),
+             f"# {'kernel':56s} {'dispatches':>10s} {'fetch_GB':>10s} {'write_GB':>10s}  (per product)"]
+    items = []
+    for k in set(fetch) | set(write):
+        if "k_copy16" in k or not k.startswith("pb::"):
+            continue  # the product's own kernels only (not the host-side checks' torch kernels)
+        prods = 4 if k.endswith(("<f64>", "<f32c>")) else 8
+        fb = fetch.get(k, 0.0) * 1024 * f_scale / prods
+        wb = write.get(k, 0.0) * 1024 * w_scale / prods
+        items.append((fb + wb, k, nf.get(k, 0), fb, wb))
+    for _, k, nd, fb, wb in sorted(items, reverse=True):
+        if fb + wb < 1e8:
+            continue
+        lines.append(f"  {k[:56]:56s} {nd:10d} {fb / 1e9:10.2f} {wb / 1e9:10.2f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize_trace(src: str, out_path: str, title: str, command: str, per=lambda name: 1) -> None:
     """Write a rocprofv3 kernel-trace stats summary (the kernels of src's
     kernel_stats.csv, longest first, with the time per product when the
@@ -827,6 +884,9 @@ def main():
     ap.add_argument("--summarize-rmat-trace", metavar="DIR",
                     help="write profiles/kernels_rmat_s20_ef16.txt from a rocprofv3 kernel trace of "
                          "`bench.py --rmat --steps 2 --warmup 1 --no-cpu-baseline` in DIR")
+    ap.add_argument("--summarize-rmat-counters", metavar="DIR",
+                    help="write profiles/hbm_traffic_rmat_s20_ef16.txt from FETCH_SIZE and WRITE_SIZE runs of "
+                         "`bench.py --quick --rmat --no-cpu-baseline` in DIR/fetch and DIR/write")
     ap.add_argument("--pmc-command", default="",
                     help="the counter command, with {COUNTER} and {KIND} for FETCH_SIZE/fetch and WRITE_SIZE/write")
     args = ap.parse_args()
@@ -839,6 +899,10 @@ def main():
                         "R-MAT scale 20 ef 16 C = A*A, FP64 and FP32c, 4 products each (plus the ER n=2^20 d=16 "
                         "steps bench.py runs first)", args.profile_command,
                         per=lambda name: 4 if ("double" in name or "float" in name) else 8)
+        return
+    if args.summarize_rmat_counters:
+        summarize_rmat_counters(args.summarize_rmat_counters,
+                                os.path.join(ROOT, "profiles", "hbm_traffic_rmat_s20_ef16.txt"), args.pmc_command)
         return
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command,
